@@ -1,0 +1,441 @@
+/*
+ * FP64 CPU oracle for histogram-sampling muon transport.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * HIP library is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may build, load or call it; the
+ * product path never does.  It shares no source with the HIP library.
+ *
+ * What it computes: the particle transport loop of the paper (Algorithm 1,
+ * "Particle Transport Simulation Loop", Section "Simulation"), one muon at a
+ * time, in double precision, with these readings of points the paper leaves
+ * open:
+ *   - sampler: exact inverse CDF over integer cumulative counts of the
+ *     flattened 2D histogram (loss index major); one Philox4x32-10 block per
+ *     material step gives the cell word and three jitter/azimuth words;
+ *   - jitter: uniform within the drawn cell on both axes (Section
+ *     "Simulation", item 2);
+ *   - kick: dp_local = |p| (tau cos phi, tau sin phi, -f), rotated into the
+ *     global frame with the Rodrigues formula of Eq. (2), axis k = z x p_hat
+ *     normalised and theta the angle between z and p_hat;
+ *   - field: per-box uniform field times the magnet's scale plus a trilinear
+ *     interpolation of a node-centred map (zero outside it), evaluated once at
+ *     the start of the step and held fixed through the RK4 stages (Algorithm
+ *     1 fetches B once before RK4Step);
+ *   - equation of motion: the Lorentz force of Eq. (3) with E = 0 written in
+ *     arc length s: dr/ds = p/|p|, dp/ds = kappa q (p/|p|) x B with
+ *     kappa = 0.299792458 GeV/(c T m), integrated with classical RK4 over the
+ *     fixed step d;
+ *   - break test: |p| < p_min, z >= z_max, |x| >= x_max, |y| >= y_max, in
+ *     that order, at the top of each iteration; the step cap ends the loop;
+ *   - containment: half-open boxes, lowest index wins; momentum bin i with
+ *     e_i <= |p| < e_{i+1}, clamped to [0, P-1].
+ *
+ * Parity pins for every function here live in tests/test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_KAPPA 0.299792458
+#define ORC_PI 3.14159265358979323846
+
+typedef struct {
+    /* histograms */
+    int32_t n_mat, n_pbin, n_loss, n_scat;
+    const double *p_edges;          /* [n_pbin+1] ascending */
+    double loss_lo, loss_hi, scat_lo, scat_hi;
+    const uint32_t *counts;         /* [n_mat][n_pbin][n_loss][n_scat] */
+    /* geometry */
+    int32_t n_box;
+    const double *box;              /* [n_box][6] xlo xhi ylo yhi zlo zhi */
+    const int32_t *material;        /* [n_box], -1 vacuum */
+    const float *b_box;             /* [n_box][3] tesla, or NULL */
+    const int32_t *magnet;          /* [n_box], -1 unscaled, or NULL */
+    int32_t n_mag;
+    double world[3];                /* x_max, y_max, z_max */
+    /* field map (nx = 0: none) */
+    int32_t nx, ny, nz;
+    double map_lo[3], map_hi[3];
+    const float *map;               /* [nz][ny][nx][3] */
+    /* run */
+    double step;
+    int32_t max_steps;
+    double p_min;
+    uint64_t seed;
+    const double *scales;           /* [n_variants][n_mag] or NULL (all 1) */
+} orc_problem;
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random      */
+/* numbers: as easy as 1, 2, 3").  Round: two 32x32->64 products of the   */
+/* even counter words with the multipliers, outputs permuted and xored    */
+/* with the odd words and the round key; the key is bumped by the Weyl    */
+/* constants between rounds.                                              */
+/* ---------------------------------------------------------------------- */
+void oracle_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t MULT_A = 0xD2511F53u, MULT_B = 0xCD9E8D57u;
+    const uint32_t WEYL_A = 0x9E3779B9u, WEYL_B = 0xBB67AE85u;
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k[2] = {key_in[0], key_in[1]};
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)MULT_A * (uint64_t)c[0];
+        uint64_t prod_b = (uint64_t)MULT_B * (uint64_t)c[2];
+        uint32_t hi_a = (uint32_t)(prod_a >> 32), lo_a = (uint32_t)prod_a;
+        uint32_t hi_b = (uint32_t)(prod_b >> 32), lo_b = (uint32_t)prod_b;
+        uint32_t n0 = hi_b ^ c[1] ^ k[0];
+        uint32_t n1 = lo_b;
+        uint32_t n2 = hi_a ^ c[3] ^ k[1];
+        uint32_t n3 = lo_a;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k[0] += WEYL_A;
+        k[1] += WEYL_B;
+    }
+    memcpy(out, c, sizeof(c));
+}
+
+/* Uniform in [0,1) from the top 24 bits of a word: exact in FP32 and FP64. */
+static double orc_unit(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+
+/* ---------------------------------------------------------------------- */
+/* Inverse CDF over integer counts.                                       */
+/* ---------------------------------------------------------------------- */
+/* Inclusive cumulative counts C[c] = sum_{c' <= c} counts[c'].  Returns 0 on
+ * success, -1 if the total is zero or does not fit in 32 bits. */
+int oracle_cdf_build(const uint32_t *counts, int64_t K, uint32_t *cdf)
+{
+    uint64_t acc = 0;
+    for (int64_t c = 0; c < K; ++c) {
+        acc += counts[c];
+        if (acc > 0xFFFFFFFFull) return -1;
+        cdf[c] = (uint32_t)acc;
+    }
+    return acc == 0 ? -1 : 0;
+}
+
+/* t = floor(w * T / 2^32), an integer uniform over [0, T) up to 2^-32. */
+uint32_t oracle_cdf_t(uint32_t w, uint32_t total)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)total) >> 32);
+}
+
+/* Smallest c with C[c] > t (upper bound), for 0 <= t < C[K-1]. */
+int64_t oracle_cdf_cell(const uint32_t *cdf, int64_t K, uint32_t t)
+{
+    int64_t lo = 0, hi = K - 1;     /* answer in [lo, hi] */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Rotation of the local kick into the global frame, Eq. (2):             */
+/*   p <- p + dp cos(theta) + (k x dp) sin(theta) + (1 - cos theta)(k.dp)k */
+/* with k the unit vector along z x p_hat and theta = angle(z, p_hat), so  */
+/* that the rotation maps the local z axis onto the direction of travel.  */
+/* ---------------------------------------------------------------------- */
+void oracle_rotate(const double p[3], const double dp[3], double out[3])
+{
+    double pm = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    double nx = p[0] / pm, ny = p[1] / pm, nz = p[2] / pm;
+    /* z x n = (-ny, nx, 0); |z x n| = sin(theta); n.z = cos(theta) */
+    double sin_t = sqrt(nx * nx + ny * ny);
+    double cos_t = nz;
+    double r[3];
+    if (sin_t == 0.0) {
+        if (cos_t > 0.0) {          /* theta = 0: identity */
+            r[0] = dp[0]; r[1] = dp[1]; r[2] = dp[2];
+        } else {                    /* theta = pi about x: (x, y, z) -> (x, -y, -z) */
+            r[0] = dp[0]; r[1] = -dp[1]; r[2] = -dp[2];
+        }
+    } else {
+        double kx = -ny / sin_t, ky = nx / sin_t, kz = 0.0;
+        double cx = ky * dp[2] - kz * dp[1];
+        double cy = kz * dp[0] - kx * dp[2];
+        double cz = kx * dp[1] - ky * dp[0];
+        double kd = kx * dp[0] + ky * dp[1] + kz * dp[2];
+        r[0] = dp[0] * cos_t + cx * sin_t + (1.0 - cos_t) * kd * kx;
+        r[1] = dp[1] * cos_t + cy * sin_t + (1.0 - cos_t) * kd * ky;
+        r[2] = dp[2] * cos_t + cz * sin_t + (1.0 - cos_t) * kd * kz;
+    }
+    out[0] = p[0] + r[0];
+    out[1] = p[1] + r[1];
+    out[2] = p[2] + r[2];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Classical RK4 on y = (r, p) with B frozen over the step.               */
+/* ---------------------------------------------------------------------- */
+static void orc_deriv(const double y[6], double q, const double B[3], double dy[6])
+{
+    double pm = sqrt(y[3] * y[3] + y[4] * y[4] + y[5] * y[5]);
+    double ux = y[3] / pm, uy = y[4] / pm, uz = y[5] / pm;
+    dy[0] = ux;
+    dy[1] = uy;
+    dy[2] = uz;
+    dy[3] = ORC_KAPPA * q * (uy * B[2] - uz * B[1]);
+    dy[4] = ORC_KAPPA * q * (uz * B[0] - ux * B[2]);
+    dy[5] = ORC_KAPPA * q * (ux * B[1] - uy * B[0]);
+}
+
+void oracle_rk4(const double y_in[6], double q, const double B[3], double h, double y_out[6])
+{
+    double k1[6], k2[6], k3[6], k4[6], t[6];
+    orc_deriv(y_in, q, B, k1);
+    for (int a = 0; a < 6; ++a) t[a] = y_in[a] + 0.5 * h * k1[a];
+    orc_deriv(t, q, B, k2);
+    for (int a = 0; a < 6; ++a) t[a] = y_in[a] + 0.5 * h * k2[a];
+    orc_deriv(t, q, B, k3);
+    for (int a = 0; a < 6; ++a) t[a] = y_in[a] + h * k3[a];
+    orc_deriv(t, q, B, k4);
+    for (int a = 0; a < 6; ++a)
+        y_out[a] = y_in[a] + h / 6.0 * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Geometry: lowest-index half-open box containing r, or -1.              */
+/* ---------------------------------------------------------------------- */
+int32_t oracle_lookup(const orc_problem *P, const double r[3])
+{
+    for (int32_t b = 0; b < P->n_box; ++b) {
+        const double *bx = P->box + 6 * b;
+        if (bx[0] <= r[0] && r[0] < bx[1] &&
+            bx[2] <= r[1] && r[1] < bx[3] &&
+            bx[4] <= r[2] && r[2] < bx[5])
+            return b;
+    }
+    return -1;
+}
+
+/* Decision margin of the lookup: the smallest distance by which r could move
+ * and change whether some box contains it. */
+static double orc_geom_margin(const orc_problem *P, const double r[3])
+{
+    double m = INFINITY;
+    for (int32_t b = 0; b < P->n_box; ++b) {
+        const double *bx = P->box + 6 * b;
+        double inside_margin = INFINITY, outside_violation = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double lo = bx[2 * a], hi = bx[2 * a + 1];
+            double dlo = r[a] - lo, dhi = hi - r[a];
+            if (dlo >= 0.0 && dhi > 0.0) {
+                double d = dlo < dhi ? dlo : dhi;
+                if (d < inside_margin) inside_margin = d;
+            } else {
+                double v = dlo < 0.0 ? -dlo : -dhi;
+                if (v > outside_violation) outside_violation = v;
+            }
+        }
+        double mb = outside_violation > 0.0 ? outside_violation : inside_margin;
+        if (mb < m) m = mb;
+    }
+    return m;
+}
+
+/* Momentum bin: e_i <= pm < e_{i+1}; below e_0 -> 0, at or above e_P -> P-1. */
+int32_t oracle_pbin(const orc_problem *P, double pm)
+{
+    int32_t n = P->n_pbin;
+    if (pm < P->p_edges[0]) return 0;
+    if (pm >= P->p_edges[n]) return n - 1;
+    int32_t lo = 0, hi = n - 1;      /* answer in [lo, hi] */
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) / 2;
+        if (P->p_edges[mid] <= pm) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Field: per-box uniform field (scaled) + trilinear map.                 */
+/* ---------------------------------------------------------------------- */
+void oracle_trilinear(const orc_problem *P, const double r[3], double B[3])
+{
+    B[0] = B[1] = B[2] = 0.0;
+    if (P->nx <= 0 || P->map == NULL) return;
+    const int32_t n[3] = {P->nx, P->ny, P->nz};
+    int32_t i0[3];
+    double w[3];
+    for (int a = 0; a < 3; ++a) {
+        if (r[a] < P->map_lo[a] || r[a] > P->map_hi[a]) return;
+        double u = (r[a] - P->map_lo[a]) / (P->map_hi[a] - P->map_lo[a]) * (double)(n[a] - 1);
+        int32_t i = (int32_t)floor(u);
+        if (i > n[a] - 2) i = n[a] - 2;
+        if (i < 0) i = 0;
+        i0[a] = i;
+        w[a] = u - (double)i;
+    }
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double wt = (dx ? w[0] : 1.0 - w[0]) * (dy ? w[1] : 1.0 - w[1]) *
+                            (dz ? w[2] : 1.0 - w[2]);
+                int64_t node = ((int64_t)(i0[2] + dz) * n[1] + (i0[1] + dy)) * n[0] + (i0[0] + dx);
+                const float *b = P->map + 3 * node;
+                B[0] += wt * (double)b[0];
+                B[1] += wt * (double)b[1];
+                B[2] += wt * (double)b[2];
+            }
+}
+
+static void orc_field(const orc_problem *P, int32_t vol, int32_t variant, const double r[3],
+                      double B[3])
+{
+    oracle_trilinear(P, r, B);
+    if (vol >= 0 && P->b_box != NULL) {
+        double s = 1.0;
+        if (P->magnet != NULL && P->magnet[vol] >= 0 && P->scales != NULL)
+            s = P->scales[(int64_t)variant * P->n_mag + P->magnet[vol]];
+        B[0] += s * (double)P->b_box[3 * vol + 0];
+        B[1] += s * (double)P->b_box[3 * vol + 1];
+        B[2] += s * (double)P->b_box[3 * vol + 2];
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* The transport loop.                                                    */
+/* ---------------------------------------------------------------------- */
+enum { ST_PMIN = 1, ST_ZMAX = 2, ST_XMAX = 3, ST_YMAX = 4, ST_STEPS = 5, ST_INVALID = 6 };
+
+typedef struct {
+    const double *x, *y, *z, *px, *py, *pz;
+    const int8_t *q;
+    const int64_t *ids;             /* Philox muon index of each muon */
+    const int32_t *variant;         /* or NULL: variant 0 */
+} orc_in;
+
+typedef struct {
+    double *x, *y, *z, *px, *py, *pz;
+    int32_t *status, *n_steps, *volume;
+    double *margin_pos, *margin_p;  /* minimum decision margins, or NULL */
+    int32_t *trace;                 /* [n][trace_steps][3] (vol, bin, cell) or NULL */
+    int32_t trace_steps;
+    float *kicks;                   /* [n][kick_steps][3] (f, tau, phi/2pi) or NULL */
+    int32_t kick_steps;
+} orc_out;
+
+static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
+                    const orc_out *out, int64_t j)
+{
+    double r[3] = {in->x[j], in->y[j], in->z[j]};
+    double p[3] = {in->px[j], in->py[j], in->pz[j]};
+    double q = (double)in->q[j];
+    int64_t mu = in->ids[j];
+    int32_t var = in->variant ? in->variant[j] : 0;
+    int32_t status = 0, k = 0;
+    double mpos = INFINITY, mp = INFINITY;
+    const int64_t K = (int64_t)P->n_loss * P->n_scat;
+    const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
+    const double wl = (P->loss_hi - P->loss_lo) / P->n_loss;
+    const double ws = (P->scat_hi - P->scat_lo) / P->n_scat;
+
+    double pm0 = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(pm0)) || pm0 == 0.0 ||
+        (in->q[j] != 1 && in->q[j] != -1))
+        status = ST_INVALID;
+
+    while (status == 0) {
+        double pm = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        /* margins of the break test */
+        double d;
+        d = fabs(pm - P->p_min) / pm;               if (d < mp) mp = d;
+        d = fabs(r[2] - P->world[2]);               if (d < mpos) mpos = d;
+        d = fabs(fabs(r[0]) - P->world[0]);         if (d < mpos) mpos = d;
+        d = fabs(fabs(r[1]) - P->world[1]);         if (d < mpos) mpos = d;
+        if (pm < P->p_min) { status = ST_PMIN; break; }
+        if (r[2] >= P->world[2]) { status = ST_ZMAX; break; }
+        if (fabs(r[0]) >= P->world[0]) { status = ST_XMAX; break; }
+        if (fabs(r[1]) >= P->world[1]) { status = ST_YMAX; break; }
+        if (k >= P->max_steps) { status = ST_STEPS; break; }
+
+        int32_t vol = oracle_lookup(P, r);
+        d = orc_geom_margin(P, r);                  if (d < mpos) mpos = d;
+        int32_t mat = vol >= 0 ? P->material[vol] : -1;
+        int32_t ibin = -1;
+        int64_t cell = -1;
+        if (mat >= 0) {
+            ibin = oracle_pbin(P, pm);
+            /* margin to the edges bracketing the chosen bin */
+            d = fabs(pm - P->p_edges[ibin]) / pm;     if (d < mp) mp = d;
+            d = fabs(pm - P->p_edges[ibin + 1]) / pm; if (d < mp) mp = d;
+            uint32_t ctr[4] = {(uint32_t)mu, (uint32_t)((uint64_t)mu >> 32), (uint32_t)k, 0u};
+            uint32_t w[4];
+            oracle_philox(ctr, key, w);
+            const uint32_t *C = cdf + ((int64_t)mat * P->n_pbin + ibin) * K;
+            uint32_t t = oracle_cdf_t(w[0], C[K - 1]);
+            cell = oracle_cdf_cell(C, K, t);
+            int64_t il = cell / P->n_scat, is = cell % P->n_scat;
+            double f = P->loss_lo + ((double)il + orc_unit(w[1])) * wl;
+            double tau = P->scat_lo + ((double)is + orc_unit(w[2])) * ws;
+            double phi = 2.0 * ORC_PI * orc_unit(w[3]);
+            double dp[3] = {pm * tau * cos(phi), pm * tau * sin(phi), -pm * f};
+            double pn[3];
+            oracle_rotate(p, dp, pn);
+            p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+            if (out->kicks && k < out->kick_steps) {
+                float *kk = out->kicks + ((int64_t)j * out->kick_steps + k) * 3;
+                kk[0] = (float)f; kk[1] = (float)tau; kk[2] = (float)orc_unit(w[3]);
+            }
+        }
+        if (out->trace && k < out->trace_steps) {
+            int32_t *tr = out->trace + ((int64_t)j * out->trace_steps + k) * 3;
+            tr[0] = vol; tr[1] = ibin; tr[2] = (int32_t)cell;
+        }
+        double B[3];
+        orc_field(P, vol, var, r, B);
+        double y[6] = {r[0], r[1], r[2], p[0], p[1], p[2]}, yn[6];
+        oracle_rk4(y, q, B, P->step, yn);
+        r[0] = yn[0]; r[1] = yn[1]; r[2] = yn[2];
+        p[0] = yn[3]; p[1] = yn[4]; p[2] = yn[5];
+        ++k;
+    }
+    out->x[j] = r[0]; out->y[j] = r[1]; out->z[j] = r[2];
+    out->px[j] = p[0]; out->py[j] = p[1]; out->pz[j] = p[2];
+    out->status[j] = status;
+    out->n_steps[j] = k;
+    out->volume[j] = status == ST_INVALID ? -1 : oracle_lookup(P, r);
+    if (status != ST_INVALID) {
+        double d = orc_geom_margin(P, r);
+        if (d < mpos) mpos = d;
+    }
+    if (out->margin_pos) out->margin_pos[j] = mpos;
+    if (out->margin_p) out->margin_p[j] = mp;
+}
+
+/* Propagate n muons.  Returns 0, or -1 for an empty/oversized histogram, or
+ * -2 when memory for the cumulative tables cannot be allocated.  Uses
+ * n_threads OpenMP threads (<= 0: the OpenMP default). */
+int oracle_propagate(const orc_problem *P, int64_t n, const orc_in *in, const orc_out *out,
+                     int32_t n_threads)
+{
+    const int64_t K = (int64_t)P->n_loss * P->n_scat;
+    const int64_t n_hist = (int64_t)P->n_mat * P->n_pbin;
+    uint32_t *cdf = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(K * n_hist > 0 ? K * n_hist : 1));
+    if (!cdf) return -2;
+    for (int64_t h = 0; h < n_hist; ++h)
+        if (oracle_cdf_build(P->counts + h * K, K, cdf + h * K) != 0) { free(cdf); return -1; }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t j = 0; j < n; ++j) orc_one(P, cdf, in, out, j);
+    free(cdf);
+    return 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

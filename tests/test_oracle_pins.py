@@ -1,0 +1,358 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every oracle function is checked here against something other than itself:
+the paper's worked example, closed forms (straight line, helix, affine
+fields), invariants (|p| conservation, orthogonality of the rotation),
+brute force on tiny inputs (integer inverse CDF), and an independent library
+implementation of Philox (rocRAND's header, compiled for the host).
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_10520_amd import workloads as W
+from tests import _custom as CU
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KAPPA = 0.299792458
+
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(HERE, "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+# ---------------------------------------------------------------- P1: bins
+def test_momentum_bins_worked_example():
+    """Section "Validation and benchmarking" (95 log10 bins, 0.18-400 GeV) and
+    the 2D-histogram figure caption (bin 118.47-128.48 GeV)."""
+    g = _golden("momentum_bins.txt")
+    e = W.log_edges(g["p_lo"], g["p_hi"], int(g["n_bins"]))
+    hits = [i for i in range(len(e) - 1)
+            if round(e[i], 2) == g["example_lo"] and round(e[i + 1], 2) == g["example_hi"]]
+    assert hits == [80]
+    assert np.all(np.diff(e) > 0)
+    ratio = e[1:] / e[:-1]
+    assert np.allclose(ratio, (g["p_hi"] / g["p_lo"]) ** (1 / g["n_bins"]), rtol=1e-12)
+
+
+def test_momentum_bin_lookup():
+    wl = W.make_workload("block", n_muons=1, n_fill=100)
+    e = wl.hist.p_edges
+    assert oracle.pbin(wl, 120.0) == 80
+    assert oracle.pbin(wl, e[80]) == 80                       # half-open: lower edge in
+    assert oracle.pbin(wl, np.nextafter(e[81], 0)) == 80
+    assert oracle.pbin(wl, e[81]) == 81
+    assert oracle.pbin(wl, 0.01) == 0                         # clamped below
+    assert oracle.pbin(wl, 1e4) == 94                         # clamped above
+    assert oracle.pbin(wl, e[-1]) == 94
+    # brute force over random momenta
+    rng = np.random.default_rng(1)
+    for pm in 10 ** rng.uniform(-0.7, 2.6, 300):
+        expect = int(np.searchsorted(e, pm, side="right") - 1)
+        assert oracle.pbin(wl, pm) == min(max(expect, 0), 94)
+    # tiny workload: 100 GeV falls in bin 24 = [89.44, 107.86] of 1-400 GeV / 32
+    t = W.make_workload("tiny", n_muons=1, n_fill=100)
+    assert oracle.pbin(t, 100.0) == 24
+    assert round(t.hist.p_edges[24], 2) == 89.44 and round(t.hist.p_edges[25], 2) == 107.86
+
+
+# ------------------------------------------------------------- P10: Philox
+def _rocrand_philox(rows):
+    inc = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+    if not os.path.exists(inc) or shutil.which("g++") is None:
+        pytest.skip("rocRAND headers or g++ not available for the independent Philox reference")
+    exe = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"philox_rocrand_{os.getpid()}")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+                    os.path.join(HERE, "philox_rocrand.cpp"), "-o", exe], check=True)
+    try:
+        inp = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    finally:
+        os.remove(exe)
+    return np.array([[int(v) for v in ln.split()] for ln in out.strip().splitlines()],
+                    dtype=np.uint64)
+
+
+def test_philox_matches_rocrand():
+    rng = np.random.default_rng(5)
+    rows = []
+    for _ in range(500):
+        klo, khi = (int(v) for v in rng.integers(0, 2 ** 32, 2))
+        c0, c2, c3 = (int(v) for v in rng.integers(0, 2 ** 32, 3))
+        c1 = int(rng.integers(0, 2 ** 29))
+        rows.append((klo, khi, c0, c1, c2, c3))
+    rows += [(0, 0, 0, 0, 0, 0), (0, 0, 12345, 0, 17, 0), (2 ** 32 - 1, 2 ** 32 - 1, 1, 2, 3, 4)]
+    ref = _rocrand_philox(rows)
+    mine = np.array([oracle.philox(r[2:], r[:2]) for r in rows], dtype=np.uint64)
+    assert np.array_equal(mine, ref)
+
+
+def test_philox_bit_balance():
+    words = np.array([oracle.philox([j, 0, 3, 0], [0, 0]) for j in range(4000)], dtype=np.uint64)
+    bits = ((words[..., None] >> np.arange(32, dtype=np.uint64)) & 1).astype(float)
+    frac = bits.mean(axis=0)                          # [4][32]
+    assert np.all(np.abs(frac - 0.5) < 5 * 0.5 / math.sqrt(4000))
+
+
+# ------------------------------------------------------- P8: inverse CDF
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_inverse_cdf_exhaustive(seed):
+    rng = np.random.default_rng(seed)
+    counts = rng.integers(0, 9, size=57).astype(np.uint32)
+    counts[rng.random(57) < 0.3] = 0
+    counts[5] = 0
+    counts[-1] = 0
+    counts[10] += 1
+    T = int(counts.sum())
+    cells = oracle.cdf_cells(counts, np.arange(T))
+    hit = np.bincount(cells, minlength=counts.size)
+    assert np.array_equal(hit, counts.astype(np.int64))      # each cell exactly count times
+    assert np.all(np.diff(cells) >= 0)                        # monotone in t
+
+
+def test_inverse_cdf_t_range():
+    for T in (1, 2, 3, 1000, 999_999, 2 ** 32 - 1):
+        assert oracle.cdf_t(0, T) == 0
+        assert oracle.cdf_t(2 ** 32 - 1, T) == T - 1
+        ws = np.linspace(0, 2 ** 32 - 1, 200).astype(np.uint64)
+        ts = [oracle.cdf_t(int(w), T) for w in ws]
+        assert np.all(np.diff(ts) >= 0) and max(ts) < T
+    # each t receives floor or ceil of 2^32/T words: count words w with t(w) = t
+    T = 7
+    edges = [math.ceil(t * 2 ** 32 / T) for t in range(T + 1)]
+    for t in range(T):
+        assert oracle.cdf_t(edges[t], T) == t
+        if edges[t] > 0:
+            assert oracle.cdf_t(edges[t] - 1, T) == t - 1
+
+
+def test_empty_histogram_rejected():
+    with pytest.raises(ValueError):
+        oracle.cdf_cells(np.zeros(10, np.uint32), [0])
+
+
+# ------------------------------------------------------- P7: rotation
+def test_rotation_maps_z_to_direction_and_is_orthogonal():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        p = rng.normal(size=3) * rng.uniform(0.5, 300)
+        if rng.random() < 0.2:
+            p[:2] *= 1e-6
+        pm = np.linalg.norm(p)
+        # R z = p_hat:  p + R (0, 0, |p|) = 2 p
+        assert np.allclose(oracle.rotate(p, [0, 0, pm]), 2 * p, rtol=0, atol=1e-13 * pm)
+        u = p / pm                                # the rotation depends on the direction only
+        R = np.stack([oracle.rotate(u, e) - u for e in np.eye(3)], axis=1)
+        assert np.allclose(R.T @ R, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1) < 1e-13
+        # the axis is perpendicular to z and p_hat: it is left unchanged
+        k = np.cross([0, 0, 1], p / pm)
+        if np.linalg.norm(k) > 1e-9:
+            k /= np.linalg.norm(k)
+            assert np.allclose(R @ k, k, atol=1e-13)
+
+
+def test_rotation_identity_along_z_and_pi_case():
+    dp = np.array([0.3, -0.2, -0.7])
+    assert np.array_equal(oracle.rotate([0, 0, 50.0], dp), np.array([0, 0, 50.0]) + dp)
+    out = oracle.rotate([0, 0, -50.0], dp) - np.array([0, 0, -50.0])
+    assert np.allclose(out, [0.3, 0.2, 0.7])
+    assert np.allclose(oracle.rotate([0, 0, -50.0], [0, 0, 50.0]), [0, 0, -100.0])
+
+
+# ------------------------------------------------------- P5: RK4 order
+def _exact_uniform(y, q, B, s):
+    """Closed-form motion in a uniform field B along y for p in the x-z plane."""
+    r, p = np.asarray(y[:3]), np.asarray(y[3:])
+    pm = np.linalg.norm(p)
+    w = KAPPA * q * B / pm                       # turn rate per metre
+    th0 = math.atan2(-p[0], p[2])
+    th = th0 + w * s
+    pn = pm * np.array([-math.sin(th), 0.0, math.cos(th)])
+    rn = r + np.array([(math.cos(th) - math.cos(th0)) / w, 0.0, (math.sin(th) - math.sin(th0)) / w])
+    return np.concatenate([rn, pn])
+
+
+def test_rk4_fifth_order_local_error():
+    y = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 5.0])
+    B = 1.7
+    errs = []
+    for h in (0.8, 0.4, 0.2):
+        num = oracle.rk4(y, 1.0, [0, B, 0], h)
+        errs.append(np.linalg.norm(num - _exact_uniform(y, 1.0, B, h)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 26 < r1 < 38 and 26 < r2 < 38, (errs, r1, r2)
+
+
+# ------------------------------------- P2-P4: transport closed forms
+def _vacuum_world(mu, b_field=None, max_steps=100, step=0.02, world=(50.0, 50.0, 1e6)):
+    hist = CU.flat_histograms()
+    if b_field is None:
+        geom = CU.geometry(np.zeros((0, 6)), np.zeros(0), world=world)
+    else:
+        geom = CU.geometry([[-1e5, 1e5, -1e5, 1e5, -1e5, 1e5]], [-1], b_box=[b_field], world=world)
+    return CU.workload(hist, geom, mu, step=step, max_steps=max_steps, p_min=0.1)
+
+
+def test_straight_line_no_field_no_material():
+    rng = np.random.default_rng(11)
+    n = 64
+    p = rng.normal(size=(3, n)) * 3
+    p[2] = np.abs(p[2]) + 5
+    mu = CU.muons(rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(-1, 1, n),
+                  p[0], p[1], p[2], np.where(np.arange(n) % 2, 1, -1))
+    wl = _vacuum_world(mu, max_steps=137)
+    res = oracle.propagate(wl)
+    assert np.all(res.status == oracle.ST_STEPS) and np.all(res.n_steps == 137)
+    st0 = mu.stacked()
+    phat = st0[3:] / np.linalg.norm(st0[3:], axis=0)
+    assert np.array_equal(res.state[3:], st0[3:])                 # p unchanged, bit for bit
+    assert np.allclose(res.state[:3], st0[:3] + 137 * 0.02 * phat, rtol=0, atol=1e-12)
+    assert np.all(res.volume == -1)
+
+
+@pytest.mark.parametrize("q", [1, -1])
+def test_helix_uniform_field(q):
+    """Radius p/(kappa B) (10 GeV in 1.7 T: 19.62 m), closed-form centre."""
+    B, pz, py = 1.7, 10.0, 0.0
+    assert abs(10.0 / (KAPPA * B) - 19.62) < 0.005
+    B = float(np.float32(B))                      # per-box fields are stored in float32
+    mu = CU.muons([0.0], [0.0], [0.0], [0.0], [py], [pz], [q])
+    n_steps = 750
+    wl = _vacuum_world(mu, b_field=[0.0, B, 0.0], max_steps=n_steps)
+    res = oracle.propagate(wl)
+    assert res.n_steps[0] == n_steps
+    ex = _exact_uniform(mu.stacked()[:, 0], q, B, n_steps * 0.02)
+    assert np.allclose(res.state[:, 0], ex, rtol=0, atol=1e-9 * 20)
+    # the orbit stays on the circle of radius R about (-q R, 0, 0)
+    R = pz / (KAPPA * B)
+    c = np.array([-q * R, 0.0, 0.0])
+    assert abs(np.linalg.norm(res.state[:3, 0] - c) - R) < 1e-9 * R
+
+
+def test_helix_with_pitch():
+    B, p = float(np.float32(1.2)), np.array([1.0, 2.0, 8.0])
+    mu = CU.muons([0.0], [0.0], [0.0], [p[0]], [p[1]], [p[2]], [1])
+    n_steps = 400
+    res = oracle.propagate(_vacuum_world(mu, b_field=[0.0, B, 0.0], max_steps=n_steps))
+    s = n_steps * 0.02
+    pm = np.linalg.norm(p)
+    # motion along B is uniform; the transverse radius is |p_perp|/(kappa B)
+    assert abs(res.state[1, 0] - s * p[1] / pm) < 1e-11
+    assert abs(res.state[4, 0] - p[1]) < 1e-12
+    pperp = math.hypot(p[0], p[2])
+    assert abs(math.hypot(res.state[3, 0], res.state[5, 0]) - pperp) < 1e-11 * pperp
+    R = pperp / (KAPPA * B)
+    # for q = +1 the centre lies at r0 + R (u0 x B_hat), the direction of the force
+    u0 = np.array([p[0], 0, p[2]]) / pperp
+    c = R * np.cross(u0, [0, 1, 0])
+    d = res.state[[0, 2], 0] - c[[0, 2]]
+    assert abs(np.linalg.norm(d) - R) < 1e-9 * R
+
+
+def test_momentum_magnitude_conserved_in_vacuum_field():
+    rng = np.random.default_rng(2)
+    n = 16
+    p = rng.normal(size=(3, n)) * 5
+    p[2] = np.abs(p[2]) + 3
+    mu = CU.muons(0, 0, 0, p[0], p[1], p[2], np.where(np.arange(n) % 2, 1, -1))
+    res = oracle.propagate(_vacuum_world(mu, b_field=[0.3, 1.7, -0.4], max_steps=1500))
+    pm0 = np.linalg.norm(p, axis=0)
+    pm1 = np.linalg.norm(res.state[3:], axis=0)
+    assert np.all(np.abs(pm1 / pm0 - 1) <= 1e-12)
+
+
+# ---------------------------------------------------- break conditions
+def test_break_order_and_statuses():
+    hist = CU.flat_histograms()
+    geom = CU.geometry(np.zeros((0, 6)), np.zeros(0), world=(1.0, 1.0, 2.0))
+    mu = CU.muons([0.0, 2.0, 0.0, 0.0, 1.0, 0.0, np.nan, 0.0, 0.0],
+                  [0.0, 0.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0],
+                  [0.0, 0.0, 0.0, 3.0, 3.0, 0.0, 0.0, 0.0, 0.0],
+                  0.0, 0.0,
+                  [0.3, 5.0, 5.0, 5.0, 5.0, 5.0, 5.0, 0.0, 5.0],
+                  [1, 1, 1, 1, 1, 1, 1, 1, 0])
+    wl = CU.workload(hist, geom, mu, p_min=0.5, max_steps=1000)
+    res = oracle.propagate(wl)
+    # p_min first, then z_max, x_max, y_max; invalid inputs flagged
+    assert list(res.status[:5]) == [oracle.ST_PMIN, oracle.ST_XMAX, oracle.ST_YMAX,
+                                    oracle.ST_ZMAX, oracle.ST_ZMAX]
+    assert list(res.n_steps[:5]) == [0, 0, 0, 0, 0]
+    # straight muon from z=0 stops at the first start with z >= 2 m: 100 steps
+    assert res.status[5] == oracle.ST_ZMAX and res.n_steps[5] == 100
+    assert list(res.status[6:]) == [oracle.ST_INVALID] * 3
+    wl0 = CU.workload(hist, geom, CU.muons(0, 0, 0, 0, 0, 5.0, 1), max_steps=0)
+    r0 = oracle.propagate(wl0)
+    assert r0.status[0] == oracle.ST_STEPS and r0.n_steps[0] == 0
+
+
+# ------------------------------------------------------- P12: geometry
+def test_geometry_half_open_lowest_index():
+    hist = CU.flat_histograms()
+    geom = CU.geometry([[0, 1, 0, 1, 0, 1], [0.5, 2, 0.5, 2, 0.5, 2], [-3, 3, -3, 3, -3, 3]],
+                       [0, 0, -1])
+    wl = CU.workload(hist, geom, CU.muons(0, 0, 0, 0, 0, 1, 1))
+    cases = {(0.7, 0.7, 0.7): 0, (1.0, 0.7, 0.7): 1, (0.5, 0.5, 0.5): 0, (0.0, 0.0, 0.0): 0,
+             (2.0, 1.0, 1.0): 2, (-1e-300, 0.0, 0.0): 2, (1.5, 1.5, 1.9999): 1,
+             (3.0, 0.0, 0.0): -1, (-3.0, -3.0, -3.0): 2}
+    for r, v in cases.items():
+        assert oracle.lookup(wl, r) == v, r
+
+
+# ------------------------------------------------------- P6: trilinear
+def _affine_map():
+    A = np.array([[0.25, -0.5, 0.125], [0.5, 0.25, -0.25], [-0.125, 0.5, 0.0625]])
+    b = np.array([0.125, -0.25, 0.5])
+    lo, hi = np.array([-2.0, -2.0, 0.0]), np.array([2.0, 2.0, 30.0])
+    nx, ny, nz = 5, 9, 31
+    xs, ys, zs = (np.linspace(lo[a], hi[a], n) for a, n in enumerate((nx, ny, nz)))
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    pts = np.stack([X, Y, Z], axis=-1)
+    vals = pts @ A.T + b
+    assert np.array_equal(vals.astype(np.float32).astype(np.float64), vals)
+    return A, b, W.FieldMap(lo=lo, hi=hi, b=vals.astype(np.float32))
+
+
+def test_trilinear_reproduces_affine_fields():
+    A, b, fmap = _affine_map()
+    hist = CU.flat_histograms()
+    geom = CU.geometry(np.zeros((0, 6)), np.zeros(0))
+    wl = CU.workload(hist, geom, CU.muons(0, 0, 0, 0, 0, 1, 1), field=fmap)
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        r = rng.uniform(fmap.lo, fmap.hi)
+        assert np.allclose(oracle.trilinear(wl, r), A @ r + b, rtol=0, atol=1e-13)
+    # node values at nodes, including the far corner
+    for r in ([-2.0, -2.0, 0.0], [2.0, 2.0, 30.0], [1.0, -0.5, 17.0]):
+        assert np.allclose(oracle.trilinear(wl, r), A @ np.array(r) + b, atol=1e-14)
+    # outside the grid the map contributes zero
+    for r in ([2.0001, 0, 1], [0, -2.5, 1], [0, 0, -0.1], [0, 0, 30.01]):
+        assert np.array_equal(oracle.trilinear(wl, r), np.zeros(3))
+
+
+def test_per_box_field_scaled_by_magnet_and_added_to_map():
+    """One straight-line step in a box with field B_box * s plus an affine map:
+    the RK4 step sees their sum (checked through the closed-form turn)."""
+    A, b, fmap = _affine_map()
+    fmap = W.FieldMap(lo=fmap.lo, hi=fmap.hi, b=np.zeros_like(fmap.b))
+    fmap.b[..., 1] = 0.5
+    hist = CU.flat_histograms()
+    geom = CU.geometry([[-1, 1, -1, 1, 0, 10]], [-1], b_box=[[0, 1.0, 0]], magnet=[0], n_mag=1)
+    mu = CU.muons(0, 0, 0.5, 0, 0, 10.0, 1)
+    scales = np.array([[0.8]])                    # map 0.5 and box 1.0 are exact in float32
+    wl = CU.workload(hist, geom, mu, max_steps=1, field=fmap, scales=scales)
+    res = oracle.propagate(wl)
+    ex = _exact_uniform(mu.stacked()[:, 0], 1, 0.8 * 1.0 + 0.5, 0.02)
+    assert np.allclose(res.state[:, 0], ex, atol=1e-12)
