@@ -1,0 +1,229 @@
+/*
+ * mt.h -- C ABI of the MI355X (gfx950) histogram-sampling muon transport.
+ *
+ * The library implements the particle transport loop of Algorithm 1
+ * ("Particle Transport Simulation Loop", Section "Simulation") for many
+ * muons at once: per step a break test, a material lookup in a set of
+ * axis-aligned boxes, a momentum-bin lookup, a draw of fractional momentum
+ * loss and transverse kick from the material's 2D histogram for that bin
+ * (exact inverse CDF over integer counts plus uniform jitter inside the
+ * cell and an isotropic azimuth), the rotation of that kick into the muon's
+ * frame with the Rodrigues formula of Eq. (2), and a fourth-order
+ * Runge-Kutta push through the magnetic field (Eq. (3) with E = 0), the
+ * field being fetched once at the start of the step.
+ *
+ * Conventions shared by every entry point:
+ *   - units: metres, GeV/c, tesla; kappa = 0.299792458 GeV/(c T m);
+ *   - every function returns an int32 status: MT_OK (0) or a negative
+ *     MT_ERR_* code; mt_last_error() then gives a message (thread-local);
+ *   - argument and shape validation is synchronous and happens before any
+ *     launch; no C++ exception crosses the ABI;
+ *   - loaders take HOST arrays, deep-copy them into library-owned device
+ *     tables and return after the copy; the caller may free its arrays at
+ *     once.  Reloading replaces the tables; do not reload while a launch that
+ *     reads them may still run;
+ *   - mt_propagate* take DEVICE pointers owned by the caller and enqueue
+ *     work on the caller's HIP stream (NULL = the null stream) without
+ *     waiting for it; the buffers must stay alive until that work is done;
+ *   - asynchronous device faults surface as MT_ERR_HIP at a later call.
+ *
+ * The library runs on the device that is current when a loader is first
+ * called; every later call must be made with that device current.
+ */
+#ifndef MT_H_
+#define MT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MT_OK               0
+#define MT_ERR_INVALID_ARG (-1)  /* null pointer, bad size, unsorted edges ... */
+#define MT_ERR_SHAPE       (-2)  /* sizes inconsistent with the loaded tables */
+#define MT_ERR_EMPTY_HIST  (-3)  /* a histogram with zero total or total >= 2^32 */
+#define MT_ERR_NOT_LOADED  (-4)  /* propagate before the tables were loaded */
+#define MT_ERR_OOM         (-5)  /* device allocation failed */
+#define MT_ERR_HIP         (-6)  /* a HIP runtime call failed */
+#define MT_ERR_LIMIT       (-7)  /* beyond a documented table limit */
+
+/* ---- per-muon status (data, not errors) ------------------------------ */
+#define MT_ST_RUNNING   0
+#define MT_ST_PMIN      1        /* |p| < p_min */
+#define MT_ST_ZMAX      2        /* z >= z_max */
+#define MT_ST_XMAX      3        /* |x| >= x_max */
+#define MT_ST_YMAX      4        /* |y| >= y_max */
+#define MT_ST_MAXSTEPS  5        /* step cap reached */
+#define MT_ST_INVALID   6        /* non-finite input, |p| = 0 or |q| != 1 */
+
+/* ---- launch forms ------------------------------------------------------ */
+#define MT_MODE_PLAIN       0    /* one lane per muon until it stops */
+#define MT_MODE_PERSISTENT  1    /* resident grid, atomic work queue, compaction */
+
+/* Documented table limits. */
+#define MT_MAX_BOXES      64     /* boxes in the geometry */
+#define MT_MAX_PBINS      1024   /* momentum bins */
+#define MT_MAX_CELLS      65536  /* n_loss * n_scat per histogram */
+#define MT_MAX_MAGNETS    16     /* scaled magnets */
+
+/*
+ * Histograms H[M][i] (Section "Building histograms"): for material m and
+ * momentum bin i, counts over n_loss linear bins of the fractional loss f in
+ * [loss_lo, loss_hi) and n_scat linear bins of the transverse kick tau =
+ * dPt/|P| in [scat_lo, scat_hi).
+ *
+ *   p_edges  host double [n_pbin+1], strictly ascending, > 0.  Bin i holds
+ *            e_i <= |p| < e_{i+1}; momenta below e_0 use bin 0, at or above
+ *            e_P use bin P-1 (no interpolation between bins).
+ *   counts   host uint32 [n_mat][n_pbin][n_loss][n_scat] (loss index major);
+ *            each histogram's total must lie in [1, 2^32).
+ * Limits: n_pbin <= MT_MAX_PBINS, n_loss * n_scat <= MT_MAX_CELLS.
+ * Errors: MT_ERR_INVALID_ARG, MT_ERR_EMPTY_HIST, MT_ERR_LIMIT, MT_ERR_OOM,
+ *         MT_ERR_HIP.
+ */
+int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges,
+                       int32_t n_loss, double loss_lo, double loss_hi,
+                       int32_t n_scat, double scat_lo, double scat_hi,
+                       const uint32_t *counts);
+
+/*
+ * Geometry (Section "Simulation", item 1, specialised to axis-aligned boxes).
+ *
+ *   box       host double [n_box][6] = xlo, xhi, ylo, yhi, zlo, zhi with
+ *             lo < hi; containment is half-open [lo, hi) on every axis and
+ *             overlapping boxes resolve to the lowest index.
+ *   material  host int32 [n_box]: material index, or -1 for vacuum (no
+ *             sampling; the box may still carry a field).
+ *   b_box     host float [n_box][3]: uniform field of the box in tesla, or
+ *             NULL for none.
+ *   magnet    host int32 [n_box] in [-1, n_mag): the field scale that
+ *             multiplies b_box (-1 = unscaled), or NULL.
+ *   world     host double [3] = x_max, y_max, z_max of the break test
+ *             |x| >= x_max, |y| >= y_max, z >= z_max.
+ * Limits: 0 <= n_box <= MT_MAX_BOXES, n_mag <= MT_MAX_MAGNETS.  Material
+ * indices must be < n_mat of the loaded histograms at propagate time.
+ */
+int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material,
+                     const float *b_box, const int32_t *magnet, int32_t n_mag,
+                     const double *world);
+
+/*
+ * Field map on a regular 3D grid (Section "Simulation", item 3), added to
+ * the per-box field and interpolated trilinearly.  Node (i, j, k) sits at
+ * lo + (i, j, k) * (hi - lo) / (n - 1); outside [lo, hi] the map gives zero.
+ *
+ *   b   host float [nz][ny][nx][3] tesla; NULL unloads the map.
+ * Requires nx, ny, nz >= 2 and lo < hi on every axis.
+ */
+int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const double *hi,
+                  const float *b);
+
+/* Device structure-of-arrays muon states (metres, GeV/c, charge +-1). */
+typedef struct mt_muons {
+    double *x, *y, *z, *px, *py, *pz;
+    int8_t *q;
+} mt_muons;
+
+/* Device per-lane outcomes. */
+typedef struct mt_result {
+    int32_t *status;    /* MT_ST_* */
+    int32_t *n_steps;   /* completed RK4 pushes */
+    int32_t *volume;    /* box containing the final position, -1 = none */
+} mt_result;
+
+/*
+ * Run parameters.  A launch processes lanes = n_variants * n muon copies: lane
+ * g = v * n + j transports input muon j under field-scale variant v and writes
+ * slot g of the outputs.  All variants of muon j draw the same random numbers
+ * (common random numbers): the Philox4x32-10 key is the 64-bit seed and the
+ * counter is (j mod 2^32, j / 2^32, step, 0).  Vacuum steps draw nothing.
+ */
+typedef struct mt_params {
+    double   step_m;          /* fixed step length d (> 0) */
+    int32_t  max_steps;       /* step cap (>= 0) */
+    double   p_min;           /* momentum threshold of the break test */
+    uint64_t seed;
+    int32_t  n_variants;      /* >= 1 */
+    const float *scales;      /* device [n_variants][n_mag] or NULL (all 1) */
+    int32_t  mode;            /* MT_MODE_PLAIN / MT_MODE_PERSISTENT */
+    int32_t  block;           /* threads per block, multiple of 64 in [64, 1024]; 0 = default */
+    int32_t  compact_every;   /* persistent: steps between refills, >= 1; 0 = default */
+    int32_t  use_graph;       /* persistent: capture the launch once as a hipGraph and replay */
+    /* differentiable form */
+    int32_t  ckpt_every;      /* 0 = off, or 16: checkpoint (r, p) every 16 steps */
+    double  *ckpt;            /* device [ceil(max_steps/16)][6][lanes] */
+    float   *tape;            /* device [max_steps][4][lanes]: local kick (3) + volume bits */
+    /* per-step trace for the first n_trace lanes */
+    int32_t *trace;           /* device [n_trace][trace_steps][3] = volume, bin, cell; or NULL */
+    int64_t  n_trace;
+    int32_t  trace_steps;
+    /* per-variant tallies at a detector plane (design scan) */
+    double  *tally;           /* device [n_variants][3] or NULL: see mt_propagate */
+    double   z_det, r_ap, r_scale;
+} mt_params;
+
+/*
+ * Transport n input muons (lanes = n_variants * n).
+ *
+ *   in    device SoA of n muons; out and res: device SoA of `lanes` entries.
+ *         out may alias in when n_variants == 1 and ckpt_every == 0.
+ *   hip_stream  hipStream_t (NULL = null stream).
+ * Per-muon outcomes are in res; status MT_ST_INVALID marks bad inputs.
+ * If params->tally is set, after transport it receives for each variant
+ * (count of lanes with status MT_ST_ZMAX, count of those whose straight-line
+ * extension reaches the plane z = z_det within radius r_ap, and the sum of
+ * sigmoid((r_ap - r)/r_scale) over them), summed in a fixed order.
+ * With use_graph, the first call for a given argument set captures
+ * queue reset + transport (+ tallies) into a hipGraph that later identical
+ * calls replay; changing any pointer or parameter captures a new graph.
+ * Errors: MT_ERR_NOT_LOADED, MT_ERR_INVALID_ARG, MT_ERR_SHAPE, MT_ERR_HIP.
+ */
+int mt_propagate(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
+                 mt_result *res, void *hip_stream);
+
+/*
+ * Pathwise adjoint of a checkpointed mt_propagate (the differentiable
+ * extension suggested in Section "Discussion and Conclusion"): sampled
+ * losses, kicks, azimuths, materials, bins and step counts are held fixed.
+ * Requires the same params, in, res, ckpt and tape as the forward call,
+ * which must have used ckpt_every = 16 and MT_MODE_PLAIN.
+ *
+ *   g_out     device double [6][lanes]: dL/d(final x, y, z, px, py, pz)
+ *   g_in      device double [6][lanes]: receives dL/d(initial state)
+ *   g_scales  device double [n_variants][n_mag] or NULL: receives dL/d(scale)
+ *             summed over each variant's lanes in a fixed order.
+ * Errors: as mt_propagate.
+ */
+int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in,
+                          const mt_result *res, const double *g_out, double *g_in,
+                          double *g_scales, void *hip_stream);
+
+/*
+ * Pick block size and refill interval of the persistent form by timing
+ * candidate launches of this exact call (blocks {64,128,256,512} x refill
+ * intervals {4,8,16,32,64,128}) on the caller's stream.  Outputs are
+ * overwritten (every candidate writes identical bits).  The choice is
+ * returned and remembered for later calls with compact_every = 0 and
+ * block = 0 on the same workload shape.
+ */
+int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
+                mt_result *res, void *hip_stream, int32_t *best_block,
+                int32_t *best_compact, float *best_ms);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *mt_last_error(void);
+
+/* Free every library-owned table, workspace and cached graph. */
+void mt_release(void);
+
+/* Device and build facts: fills info[0..3] = compute units, XCD count guess,
+ * LDS bytes per block, wave size.  For reports only. */
+int mt_device_info(int32_t *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MT_H_ */

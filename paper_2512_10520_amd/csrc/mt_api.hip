@@ -1,0 +1,734 @@
+// Host side of the C ABI declared in include/mt.h: validation, table
+// building (cumulative counts, inverse-CDF guide, z-slab grid, float4 field),
+// launch dispatch, hipGraph cache for the persistent form and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mt_internal.h"
+
+namespace {
+
+using mt::Tables;
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define MT_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(MT_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+// A device buffer owned by the library.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Grow to at least n bytes (contents not preserved).
+    int ensure(size_t n) {
+        if (n <= bytes && p) return MT_OK;
+        release();
+        if (n == 0) n = 16;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MT_ERR_OOM, "device allocation of %zu bytes failed", n);
+        }
+        bytes = n;
+        return MT_OK;
+    }
+    int upload(const void *src, size_t n) {
+        int rc = ensure(n);
+        if (rc) return rc;
+        if (n && hipMemcpy(p, src, n, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MT_ERR_HIP, "hipMemcpy of %zu bytes failed", n);
+        return MT_OK;
+    }
+};
+
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct TuneEntry {
+    std::vector<unsigned char> key;
+    int block = 0, compact = 0;
+};
+
+struct State {
+    std::mutex mu;
+    int device = -1;
+    bool hist_loaded = false, geom_loaded = false;
+    int n_mat = 0, n_pbin = 0;
+    int64_t version = 0;  // bumped on every table change
+    DevBuf cdf, guide, totals, edges2;
+    DevBuf box4, material, bfield, magnet, slab_z, slab_mask;
+    DevBuf map;
+    DevBuf queue, partial, scratch, gs_lane, zero_dummy;
+    Tables T{};
+    int max_material = -1;
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+    std::vector<TuneEntry> tuned;
+    int cu_count = 0;
+};
+
+State g;
+
+int ensure_device() {
+    if (g.device < 0) {
+        int d = 0;
+        if (hipGetDevice(&d) != hipSuccess) return fail(MT_ERR_HIP, "no HIP device is available");
+        g.device = d;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, d) == hipSuccess) g.cu_count = prop.multiProcessorCount;
+        if (g.cu_count <= 0) g.cu_count = 256;
+    }
+    return MT_OK;
+}
+
+void drop_graphs() {
+    for (auto &e : g.graphs) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+    }
+    g.graphs.clear();
+}
+
+void tables_changed() {
+    ++g.version;
+    drop_graphs();
+    g.tuned.clear();
+}
+
+// LDS layout of the staged tables (depends on histogram and geometry sizes).
+void relayout() {
+    mt::LdsLayout L{};
+    int off = 0;
+    auto take = [&](int bytes, int align) {
+        off = (off + align - 1) / align * align;
+        const int o = off;
+        off += bytes;
+        return o;
+    };
+    const int P = g.T.hist.n_pbin, nb = g.T.geom.n_box, ns = g.T.geom.n_slab;
+    const int nh = g.T.hist.n_mat * P;
+    L.off_e2 = take(8 * (P + 1), 16);
+    L.totals_in_lds = nh <= mt::kTotalsLdsMax ? 1 : 0;
+    L.off_tot = take(L.totals_in_lds ? 4 * nh : 0, 16);
+    L.off_box4 = take(32 * nb, 16);
+    L.off_bf = take(16 * nb, 16);
+    L.off_mat = take(4 * nb, 16);
+    L.off_mag = take(4 * nb, 16);
+    L.off_slabz = take(8 * (ns + 1), 16);
+    L.off_slabm = take(8 * ns, 16);
+    L.bytes = (off + 15) / 16 * 16;
+    g.T.lds = L;
+}
+
+std::vector<unsigned char> make_key(const void *a, size_t na, const void *b = nullptr,
+                                    size_t nb = 0) {
+    std::vector<unsigned char> k(na + nb + sizeof(int64_t));
+    std::memcpy(k.data(), a, na);
+    if (nb) std::memcpy(k.data() + na, b, nb);
+    std::memcpy(k.data() + na + nb, &g.version, sizeof(int64_t));
+    return k;
+}
+
+// Validated, device-side description of one propagate call.
+struct Call {
+    mt::DevRun R{};
+    mt::DevIO io{};
+    int block = 256;
+    int compact = 16;
+    int n_variants = 1;
+    int64_t n = 0, lanes = 0;
+};
+
+int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *out,
+             const mt_result *res, bool backward, Call &c) {
+    if (!g.hist_loaded || !g.geom_loaded)
+        return fail(MT_ERR_NOT_LOADED, "histograms and geometry must be loaded before propagating");
+    if (!p) return fail(MT_ERR_INVALID_ARG, "params is NULL");
+    if (n < 0) return fail(MT_ERR_INVALID_ARG, "n = %lld is negative", (long long)n);
+    if (p->n_variants < 1) return fail(MT_ERR_INVALID_ARG, "n_variants must be >= 1");
+    if (n > 0 && p->n_variants > std::numeric_limits<int64_t>::max() / n)
+        return fail(MT_ERR_INVALID_ARG, "n_variants * n overflows");
+    if (!(p->step_m > 0.0) || !std::isfinite(p->step_m))
+        return fail(MT_ERR_INVALID_ARG, "step_m must be finite and > 0");
+    if (p->max_steps < 0) return fail(MT_ERR_INVALID_ARG, "max_steps must be >= 0");
+    if (!(p->p_min >= 0.0) || !std::isfinite(p->p_min))
+        return fail(MT_ERR_INVALID_ARG, "p_min must be finite and >= 0");
+    if (p->mode != MT_MODE_PLAIN && p->mode != MT_MODE_PERSISTENT)
+        return fail(MT_ERR_INVALID_ARG, "unknown mode %d", p->mode);
+    if (p->block != 0 && (p->block < 64 || p->block > 1024 || p->block % 64 != 0))
+        return fail(MT_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+    if (p->compact_every < 0) return fail(MT_ERR_INVALID_ARG, "compact_every must be >= 0");
+    if (p->ckpt_every != 0 && p->ckpt_every != mt::kCkptEvery)
+        return fail(MT_ERR_INVALID_ARG, "ckpt_every must be 0 or %d", mt::kCkptEvery);
+    if (p->ckpt_every != 0) {
+        if (!p->ckpt || !p->tape)
+            return fail(MT_ERR_INVALID_ARG, "checkpointing needs both ckpt and tape buffers");
+        if (p->mode != MT_MODE_PLAIN)
+            return fail(MT_ERR_INVALID_ARG, "checkpointing is only supported in MT_MODE_PLAIN");
+    }
+    if (backward && p->ckpt_every == 0)
+        return fail(MT_ERR_INVALID_ARG, "the backward pass needs the checkpointed forward's "
+                                        "ckpt_every, ckpt and tape");
+    if (p->n_trace < 0 || p->trace_steps < 0)
+        return fail(MT_ERR_INVALID_ARG, "n_trace and trace_steps must be >= 0");
+    if (p->n_trace > 0 && p->trace_steps > 0 && !p->trace)
+        return fail(MT_ERR_INVALID_ARG, "trace buffer is NULL");
+    if (p->scales && g.T.geom.n_mag == 0)
+        return fail(MT_ERR_SHAPE, "scales given but the geometry has no magnets");
+    if (p->tally && !(p->r_scale > 0.0))
+        return fail(MT_ERR_INVALID_ARG, "tally needs r_scale > 0");
+    if (g.max_material >= g.n_mat)
+        return fail(MT_ERR_SHAPE, "geometry uses material %d but histograms hold %d materials",
+                    g.max_material, g.n_mat);
+    if (n > 0) {
+        if (!in || !in->x || !in->y || !in->z || !in->px || !in->py || !in->pz || !in->q)
+            return fail(MT_ERR_INVALID_ARG, "input muon pointers must be non-NULL");
+        if (!res || !res->status || !res->n_steps || !res->volume)
+            return fail(MT_ERR_INVALID_ARG, "result pointers must be non-NULL");
+        if (!backward && (!out || !out->x || !out->y || !out->z || !out->px || !out->py ||
+                          !out->pz))
+            return fail(MT_ERR_INVALID_ARG, "output muon pointers must be non-NULL");
+    }
+    c.n = n;
+    c.n_variants = p->n_variants;
+    c.lanes = n * p->n_variants;
+    c.block = p->block ? p->block : 256;
+    c.compact = p->compact_every ? p->compact_every : 16;
+    mt::DevRun &R = c.R;
+    R.h = p->step_m;
+    R.pmin2 = p->p_min * p->p_min;
+    R.max_steps = p->max_steps;
+    R.key0 = (uint32_t)p->seed;
+    R.key1 = (uint32_t)(p->seed >> 32);
+    R.n = n;
+    R.lanes = c.lanes;
+    R.scales = p->scales;
+    R.ckpt = p->ckpt_every ? p->ckpt : nullptr;
+    R.tape = p->ckpt_every ? p->tape : nullptr;
+    R.trace = p->trace;
+    R.n_trace = (p->trace && p->trace_steps > 0) ? p->n_trace : 0;
+    R.trace_steps = p->trace_steps;
+    mt::DevIO &io = c.io;
+    if (n > 0) {
+        io.x = in->x; io.y = in->y; io.z = in->z;
+        io.px = in->px; io.py = in->py; io.pz = in->pz; io.q = in->q;
+        if (out) {
+            io.ox = out->x; io.oy = out->y; io.oz = out->z;
+            io.opx = out->px; io.opy = out->py; io.opz = out->pz;
+        }
+        io.status = res->status; io.n_steps = res->n_steps; io.volume = res->volume;
+    }
+    return MT_OK;
+}
+
+int n_part_blocks(int64_t n) {
+    int64_t nb = (n + 4095) / 4096;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256));
+}
+
+// Enqueue transport (+ tallies) on stream s.  With `reset` the persistent
+// queue and the tally outputs are cleared by a kernel first.
+int enqueue(const mt_params *p, const Call &c, hipStream_t s) {
+    if (p->mode == MT_MODE_PERSISTENT) {
+        int rc = g.queue.ensure(sizeof(unsigned long long));
+        if (rc) return rc;
+        MT_HIP(mt::launch_queue_reset(reinterpret_cast<unsigned long long *>(g.queue.p),
+                                      reinterpret_cast<double *>(g.zero_dummy.p), 0, s));
+        const int grid = g.cu_count * mt::persistent_blocks_per_cu(g.T, c.block);
+        MT_HIP(mt::launch_persistent(g.T, c.R, c.io, c.block, grid, c.compact,
+                                     reinterpret_cast<unsigned long long *>(g.queue.p), s));
+    } else {
+        MT_HIP(mt::launch_plain(g.T, c.R, c.io, c.block, s));
+    }
+    if (p->tally) {
+        const int nb = n_part_blocks(c.n);
+        MT_HIP(mt::launch_tally(c.io, c.n, c.n_variants, p->z_det, p->r_ap, p->r_scale,
+                                reinterpret_cast<double *>(g.partial.p), nb, p->tally, s));
+    }
+    return MT_OK;
+}
+
+int prepare_workspace(const mt_params *p, const Call &c) {
+    int rc = g.queue.ensure(sizeof(unsigned long long));
+    if (rc) return rc;
+    rc = g.zero_dummy.ensure(16);
+    if (rc) return rc;
+    if (p->tally) {
+        rc = g.partial.ensure((size_t)n_part_blocks(c.n) * c.n_variants * 3 * sizeof(double));
+        if (rc) return rc;
+    }
+    return MT_OK;
+}
+
+const TuneEntry *find_tuned(const std::vector<unsigned char> &key) {
+    for (auto &t : g.tuned)
+        if (t.key == key) return &t;
+    return nullptr;
+}
+
+std::vector<unsigned char> tune_key(const mt_params *p, int64_t n) {
+    struct K {
+        int64_t n;
+        int32_t nv, max_steps, has_map, mode;
+        double step, pmin;
+    } k{n, p->n_variants, p->max_steps, g.T.field.map != nullptr, p->mode, p->step_m, p->p_min};
+    return make_key(&k, sizeof(k));
+}
+
+int propagate_impl(const mt_params *p, int64_t n, const mt_muons *in, mt_muons *out,
+                   mt_result *res, void *hip_stream, int force_block, int force_compact,
+                   bool allow_graph) {
+    Call c;
+    int rc = validate(p, n, in, out, res, false, c);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (c.lanes == 0) {
+        if (p->tally) {
+            if ((rc = g.queue.ensure(sizeof(unsigned long long)))) return rc;
+            MT_HIP(mt::launch_queue_reset(reinterpret_cast<unsigned long long *>(g.queue.p),
+                                          p->tally, (int64_t)p->n_variants * 3, s));
+        }
+        return MT_OK;
+    }
+    if (p->mode == MT_MODE_PERSISTENT && p->block == 0 && p->compact_every == 0) {
+        if (const TuneEntry *t = find_tuned(tune_key(p, n))) {
+            c.block = t->block;
+            c.compact = t->compact;
+        }
+    }
+    if (force_block) c.block = force_block;
+    if (force_compact) c.compact = force_compact;
+    rc = prepare_workspace(p, c);
+    if (rc) return rc;
+    if (allow_graph && p->use_graph && p->mode == MT_MODE_PERSISTENT) {
+        struct K {
+            mt_params p;
+            int64_t n;
+            mt_muons in, out;
+            mt_result res;
+            int block, compact;
+        } k;
+        std::memset(&k, 0, sizeof(k));
+        k.p = *p;
+        k.n = n;
+        k.in = *in;
+        k.out = *out;
+        k.res = *res;
+        k.block = c.block;
+        k.compact = c.compact;
+        std::vector<unsigned char> key = make_key(&k, sizeof(k));
+        GraphEntry *hit = nullptr;
+        for (auto &e : g.graphs)
+            if (e.key == key) hit = &e;
+        if (!hit) {
+            if (!g.cap_stream) MT_HIP(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking));
+            if (g.graphs.size() >= 8) {
+                GraphEntry &old = g.graphs.front();
+                if (old.exec) (void)hipGraphExecDestroy(old.exec);
+                if (old.graph) (void)hipGraphDestroy(old.graph);
+                g.graphs.erase(g.graphs.begin());
+            }
+            GraphEntry e;
+            e.key = key;
+            MT_HIP(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal));
+            int erc = enqueue(p, c, g.cap_stream);
+            hipGraph_t graph = nullptr;
+            hipError_t ec = hipStreamEndCapture(g.cap_stream, &graph);
+            if (erc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return erc;
+            }
+            if (ec != hipSuccess)
+                return fail(MT_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+            e.graph = graph;
+            MT_HIP(hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0));
+            g.graphs.push_back(e);
+            hit = &g.graphs.back();
+        }
+        MT_HIP(hipGraphLaunch(hit->exec, s));
+        return MT_OK;
+    }
+    return enqueue(p, c, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int32_t n_loss,
+                       double loss_lo, double loss_hi, int32_t n_scat, double scat_lo,
+                       double scat_hi, const uint32_t *counts) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    int rc = MT_OK;
+    if (n_mat < 1 || n_pbin < 1 || n_loss < 1 || n_scat < 1)
+        return fail(MT_ERR_INVALID_ARG, "n_mat, n_pbin, n_loss and n_scat must be >= 1");
+    if (!p_edges || !counts) return fail(MT_ERR_INVALID_ARG, "p_edges and counts must be non-NULL");
+    if (n_pbin > MT_MAX_PBINS)
+        return fail(MT_ERR_LIMIT, "n_pbin = %d exceeds %d", n_pbin, MT_MAX_PBINS);
+    const int64_t K = (int64_t)n_loss * n_scat;
+    if (K > MT_MAX_CELLS)
+        return fail(MT_ERR_LIMIT, "n_loss * n_scat = %lld exceeds %d", (long long)K, MT_MAX_CELLS);
+    if (!(loss_hi > loss_lo) || !(scat_hi > scat_lo) || !std::isfinite(loss_lo) ||
+        !std::isfinite(loss_hi) || !std::isfinite(scat_lo) || !std::isfinite(scat_hi))
+        return fail(MT_ERR_INVALID_ARG, "axis ranges must be finite with hi > lo");
+    for (int i = 0; i <= n_pbin; ++i) {
+        if (!std::isfinite(p_edges[i]) || !(p_edges[i] > 0.0))
+            return fail(MT_ERR_INVALID_ARG, "p_edges[%d] must be finite and > 0", i);
+        if (i > 0 && !(p_edges[i] > p_edges[i - 1]))
+            return fail(MT_ERR_INVALID_ARG, "p_edges must be strictly ascending (index %d)", i);
+    }
+    const int64_t nh = (int64_t)n_mat * n_pbin;
+    // Guide resolution: about one guide entry per cell, at most 2^16.
+    int gbits = 1;
+    while (gbits < 16 && ((int64_t)1 << gbits) < K) ++gbits;
+    if (gbits > 1) --gbits;
+    if (const char *env = std::getenv("MT_GUIDE_BITS")) {
+        int v = std::atoi(env);
+        if (v >= 1 && v <= 16) gbits = v;
+    }
+    const int64_t G = (int64_t)1 << gbits;
+    std::vector<uint32_t> cdf((size_t)(nh * K)), guide((size_t)(nh * G)), totals((size_t)nh);
+    for (int64_t h = 0; h < nh; ++h) {
+        uint64_t acc = 0;
+        const uint32_t *src = counts + h * K;
+        uint32_t *C = cdf.data() + h * K;
+        for (int64_t c = 0; c < K; ++c) {
+            acc += src[c];
+            if (acc > 0xFFFFFFFFull)
+                return fail(MT_ERR_EMPTY_HIST, "histogram %lld: total count does not fit in 32 bits",
+                            (long long)h);
+            C[c] = (uint32_t)acc;
+        }
+        if (acc == 0)
+            return fail(MT_ERR_EMPTY_HIST, "histogram %lld (material %lld, bin %lld) is empty",
+                        (long long)h, (long long)(h / n_pbin), (long long)(h % n_pbin));
+        const uint64_t T = acc;
+        totals[(size_t)h] = (uint32_t)T;
+        auto cell_of = [&](uint32_t t) {
+            return (uint32_t)(std::upper_bound(C, C + K, t) - C);
+        };
+        uint32_t *Gd = guide.data() + h * G;
+        for (int64_t gi = 0; gi < G; ++gi) {
+            const uint64_t w_lo = (uint64_t)gi << (32 - gbits);
+            const uint64_t w_hi = (((uint64_t)gi + 1) << (32 - gbits)) - 1;
+            const uint32_t lo = cell_of((uint32_t)((w_lo * T) >> 32));
+            const uint32_t hi = cell_of((uint32_t)((w_hi * T) >> 32));
+            Gd[gi] = lo | (hi << 16);
+        }
+    }
+    std::vector<double> e2((size_t)n_pbin + 1);
+    for (int i = 0; i <= n_pbin; ++i) e2[i] = p_edges[i] * p_edges[i];
+    if ((rc = ensure_device())) return rc;
+    if ((rc = g.cdf.upload(cdf.data(), cdf.size() * 4))) return rc;
+    if ((rc = g.guide.upload(guide.data(), guide.size() * 4))) return rc;
+    if ((rc = g.totals.upload(totals.data(), totals.size() * 4))) return rc;
+    if ((rc = g.edges2.upload(e2.data(), e2.size() * 8))) return rc;
+    mt::DevHist &H = g.T.hist;
+    H.cdf = reinterpret_cast<const uint32_t *>(g.cdf.p);
+    H.guide = reinterpret_cast<const uint32_t *>(g.guide.p);
+    H.totals = reinterpret_cast<const uint32_t *>(g.totals.p);
+    H.edges2 = reinterpret_cast<const double *>(g.edges2.p);
+    H.n_mat = n_mat;
+    H.n_pbin = n_pbin;
+    H.n_loss = n_loss;
+    H.n_scat = n_scat;
+    H.n_cells = (int32_t)K;
+    H.gbits = gbits;
+    H.nscat_magic = (uint32_t)((0x100000000ull / (uint64_t)n_scat) + 1);
+    H.loss_lo = (float)loss_lo;
+    H.loss_w = (float)((loss_hi - loss_lo) / n_loss);
+    H.scat_lo = (float)scat_lo;
+    H.scat_w = (float)((scat_hi - scat_lo) / n_scat);
+    g.n_mat = n_mat;
+    g.n_pbin = n_pbin;
+    g.hist_loaded = true;
+    relayout();
+    tables_changed();
+    return MT_OK;
+}
+
+int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material, const float *b_box,
+                     const int32_t *magnet, int32_t n_mag, const double *world) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    int rc = MT_OK;
+    if (n_box < 0 || n_box > MT_MAX_BOXES)
+        return fail(n_box < 0 ? MT_ERR_INVALID_ARG : MT_ERR_LIMIT, "n_box = %d not in [0, %d]",
+                    n_box, MT_MAX_BOXES);
+    if (n_mag < 0 || n_mag > MT_MAX_MAGNETS)
+        return fail(n_mag < 0 ? MT_ERR_INVALID_ARG : MT_ERR_LIMIT, "n_mag = %d not in [0, %d]",
+                    n_mag, MT_MAX_MAGNETS);
+    if (!world) return fail(MT_ERR_INVALID_ARG, "world must be non-NULL");
+    if (n_box > 0 && (!box || !material))
+        return fail(MT_ERR_INVALID_ARG, "box and material must be non-NULL");
+    for (int a = 0; a < 3; ++a)
+        if (std::isnan(world[a])) return fail(MT_ERR_INVALID_ARG, "world[%d] is NaN", a);
+    std::vector<double> box4((size_t)4 * n_box);
+    std::vector<float4> bf((size_t)n_box);
+    std::vector<int32_t> mat((size_t)n_box), mag((size_t)n_box);
+    std::vector<double> zs;
+    int max_mat = -1;
+    for (int b = 0; b < n_box; ++b) {
+        const double *bx = box + 6 * b;
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(bx[2 * a]) || !std::isfinite(bx[2 * a + 1]) || !(bx[2 * a] < bx[2 * a + 1]))
+                return fail(MT_ERR_INVALID_ARG, "box %d: bounds must be finite with lo < hi", b);
+        box4[4 * b + 0] = bx[0];
+        box4[4 * b + 1] = bx[1];
+        box4[4 * b + 2] = bx[2];
+        box4[4 * b + 3] = bx[3];
+        zs.push_back(bx[4]);
+        zs.push_back(bx[5]);
+        if (material[b] < -1) return fail(MT_ERR_INVALID_ARG, "material[%d] < -1", b);
+        mat[b] = material[b];
+        max_mat = std::max(max_mat, material[b]);
+        const int m = magnet ? magnet[b] : -1;
+        if (m < -1 || m >= n_mag)
+            return fail(MT_ERR_INVALID_ARG, "magnet[%d] = %d not in [-1, n_mag)", b, m);
+        mag[b] = m;
+        bf[b] = b_box ? make_float4(b_box[3 * b], b_box[3 * b + 1], b_box[3 * b + 2], 0.f)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    std::sort(zs.begin(), zs.end());
+    zs.erase(std::unique(zs.begin(), zs.end()), zs.end());
+    std::vector<double> slab_z;
+    slab_z.push_back(-std::numeric_limits<double>::infinity());
+    for (double z : zs) slab_z.push_back(z);
+    slab_z.push_back(std::numeric_limits<double>::infinity());
+    const int n_slab = (int)slab_z.size() - 1;
+    std::vector<uint64_t> mask((size_t)n_slab, 0ull);
+    for (int s = 0; s < n_slab; ++s)
+        for (int b = 0; b < n_box; ++b)
+            if (box[6 * b + 4] <= slab_z[s] && slab_z[s + 1] <= box[6 * b + 5])
+                mask[s] |= 1ull << b;
+    if ((rc = ensure_device())) return rc;
+    if ((rc = g.box4.upload(box4.data(), box4.size() * 8))) return rc;
+    if ((rc = g.bfield.upload(bf.data(), bf.size() * 16))) return rc;
+    if ((rc = g.material.upload(mat.data(), mat.size() * 4))) return rc;
+    if ((rc = g.magnet.upload(mag.data(), mag.size() * 4))) return rc;
+    if ((rc = g.slab_z.upload(slab_z.data(), slab_z.size() * 8))) return rc;
+    if ((rc = g.slab_mask.upload(mask.data(), mask.size() * 8))) return rc;
+    mt::DevGeom &G = g.T.geom;
+    G.n_box = n_box;
+    G.n_slab = n_slab;
+    G.n_mag = n_mag;
+    G.box4 = reinterpret_cast<const double *>(g.box4.p);
+    G.material = reinterpret_cast<const int32_t *>(g.material.p);
+    G.bfield = reinterpret_cast<const float4 *>(g.bfield.p);
+    G.magnet = reinterpret_cast<const int32_t *>(g.magnet.p);
+    G.slab_z = reinterpret_cast<const double *>(g.slab_z.p);
+    G.slab_mask = reinterpret_cast<const uint64_t *>(g.slab_mask.p);
+    G.x_max = world[0];
+    G.y_max = world[1];
+    G.z_max = world[2];
+    g.max_material = max_mat;
+    g.geom_loaded = true;
+    relayout();
+    tables_changed();
+    return MT_OK;
+}
+
+int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const double *hi,
+                  const float *b) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    int rc = MT_OK;
+    if (!b) {
+        g.map.release();
+        g.T.field = mt::DevField{};
+        tables_changed();
+        return MT_OK;
+    }
+    if (nx < 2 || ny < 2 || nz < 2) return fail(MT_ERR_INVALID_ARG, "nx, ny, nz must be >= 2");
+    if (!lo || !hi) return fail(MT_ERR_INVALID_ARG, "lo and hi must be non-NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] > lo[a]))
+            return fail(MT_ERR_INVALID_ARG, "field bounds must be finite with hi > lo (axis %d)", a);
+    const size_t nodes = (size_t)nx * ny * nz;
+    std::vector<float4> m(nodes);
+    for (size_t i = 0; i < nodes; ++i) m[i] = make_float4(b[3 * i], b[3 * i + 1], b[3 * i + 2], 0.f);
+    if ((rc = ensure_device())) return rc;
+    if ((rc = g.map.upload(m.data(), nodes * 16))) return rc;
+    mt::DevField &F = g.T.field;
+    F.map = reinterpret_cast<const float4 *>(g.map.p);
+    F.nx = nx;
+    F.ny = ny;
+    F.nz = nz;
+    const int n[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        F.lo[a] = lo[a];
+        F.inv_d[a] = (double)(n[a] - 1) / (hi[a] - lo[a]);
+    }
+    tables_changed();
+    return MT_OK;
+}
+
+int mt_propagate(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
+                 mt_result *res, void *hip_stream) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    return propagate_impl(params, n, in, out, res, hip_stream, 0, 0, true);
+}
+
+int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in,
+                          const mt_result *res, const double *g_out, double *g_in,
+                          double *g_scales, void *hip_stream) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    Call c;
+    int rc = validate(params, n, in, nullptr, res, true, c);
+    if (rc) return rc;
+    if (params->mode != MT_MODE_PLAIN)
+        return fail(MT_ERR_INVALID_ARG, "the backward pass follows a MT_MODE_PLAIN forward");
+    if (c.lanes > 0 && (!g_out || !g_in))
+        return fail(MT_ERR_INVALID_ARG, "g_out and g_in must be non-NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const int n_mag = g.T.geom.n_mag;
+    if (c.lanes == 0) {
+        if (g_scales && n_mag > 0) {
+            rc = g.queue.ensure(8);
+            if (rc) return rc;
+            MT_HIP(mt::launch_queue_reset(reinterpret_cast<unsigned long long *>(g.queue.p),
+                                          g_scales, (int64_t)params->n_variants * n_mag, s));
+        }
+        return MT_OK;
+    }
+    if ((rc = g.scratch.ensure((size_t)mt::adjoint_scratch_bytes(g.T, c.lanes)))) return rc;
+    if ((rc = g.gs_lane.ensure((size_t)std::max(1, n_mag) * c.lanes * sizeof(double)))) return rc;
+    const int block = 256;
+    MT_HIP(mt::launch_adjoint(g.T, c.R, c.io, g_out, g_in,
+                              reinterpret_cast<double *>(g.gs_lane.p), g.scratch.p, block, s));
+    if (g_scales && n_mag > 0) {
+        const int nb = n_part_blocks(c.n);
+        if ((rc = g.partial.ensure((size_t)nb * c.n_variants * n_mag * sizeof(double)))) return rc;
+        MT_HIP(mt::launch_column_sums(reinterpret_cast<const double *>(g.gs_lane.p), n_mag, c.n,
+                                      c.n_variants, reinterpret_cast<double *>(g.partial.p), nb,
+                                      g_scales, s));
+    }
+    return MT_OK;
+}
+
+int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
+                mt_result *res, void *hip_stream, int32_t *best_block, int32_t *best_compact,
+                float *best_ms) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    if (!params) return fail(MT_ERR_INVALID_ARG, "params is NULL");
+    if (params->mode != MT_MODE_PERSISTENT)
+        return fail(MT_ERR_INVALID_ARG, "the autotuner tunes MT_MODE_PERSISTENT launches");
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const int blocks[] = {64, 128, 256, 512};
+    const int compacts[] = {4, 8, 16, 32, 64, 128};
+    hipEvent_t e0, e1;
+    MT_HIP(hipEventCreate(&e0));
+    MT_HIP(hipEventCreate(&e1));
+    float best = std::numeric_limits<float>::infinity();
+    int bb = 256, bc = 16;
+    mt_params p = *params;
+    p.tally = nullptr;
+    p.use_graph = 0;
+    int rc = MT_OK;
+    for (int b : blocks) {
+        for (int cpt : compacts) {
+            rc = propagate_impl(&p, n, in, out, res, hip_stream, b, cpt, false);   // warm-up
+            if (rc) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MT_ERR_HIP, "hipEventRecord failed"); break; }
+            const int reps = 2;
+            for (int r = 0; r < reps && !rc; ++r)
+                rc = propagate_impl(&p, n, in, out, res, hip_stream, b, cpt, false);
+            if (rc) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(MT_ERR_HIP, "event timing failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (ms < best) {
+                best = ms;
+                bb = b;
+                bc = cpt;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    std::vector<unsigned char> key = tune_key(params, n);
+    bool found = false;
+    for (auto &t : g.tuned)
+        if (t.key == key) {
+            t.block = bb;
+            t.compact = bc;
+            found = true;
+        }
+    if (!found) g.tuned.push_back(TuneEntry{key, bb, bc});
+    drop_graphs();
+    if (best_block) *best_block = bb;
+    if (best_compact) *best_compact = bc;
+    if (best_ms) *best_ms = best;
+    return MT_OK;
+}
+
+const char *mt_last_error(void) { return g_err.c_str(); }
+
+void mt_release(void) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    drop_graphs();
+    for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.box4, &g.material, &g.bfield,
+                      &g.magnet, &g.slab_z, &g.slab_mask, &g.map, &g.queue, &g.partial,
+                      &g.scratch, &g.gs_lane, &g.zero_dummy})
+        b->release();
+    if (g.cap_stream) {
+        (void)hipStreamDestroy(g.cap_stream);
+        g.cap_stream = nullptr;
+    }
+    g.T = Tables{};
+    g.hist_loaded = g.geom_loaded = false;
+    g.n_mat = g.n_pbin = 0;
+    g.max_material = -1;
+    g.tuned.clear();
+    ++g.version;
+}
+
+int mt_device_info(int32_t *info) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    if (!info) return fail(MT_ERR_INVALID_ARG, "info is NULL");
+    int rc = ensure_device();
+    if (rc) return rc;
+    hipDeviceProp_t prop;
+    MT_HIP(hipGetDeviceProperties(&prop, g.device));
+    info[0] = prop.multiProcessorCount;
+    info[1] = 8;
+    info[2] = (int32_t)prop.sharedMemPerBlock;
+    info[3] = prop.warpSize;
+    return MT_OK;
+}
+
+}  // extern "C"

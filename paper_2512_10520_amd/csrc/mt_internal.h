@@ -1,0 +1,110 @@
+// Private structures shared by the host API (mt_api.hip) and the kernels
+// (mt_kernels.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mt.h"
+
+namespace mt {
+
+constexpr int kWave = 64;
+constexpr int kCkptEvery = 16;             // RK4 state checkpoint interval
+constexpr int kTotalsLdsMax = 4096;        // histogram totals staged in LDS up to this many
+constexpr double kKappa = 0.299792458;     // GeV / (c T m)
+
+// Histogram tables on the device.  cdf[h][c] is the inclusive cumulative
+// count of cell c of histogram h = material * n_pbin + bin; guide[h][g]
+// brackets the answer of the inverse-CDF search for every word whose top
+// gbits bits equal g (low 16 bits: first candidate cell, high 16 bits: last).
+struct DevHist {
+    const uint32_t *cdf;
+    const uint32_t *guide;       // nullptr: search the whole row
+    const uint32_t *totals;      // [n_hist]
+    const double *edges2;        // [n_pbin + 1] squared momentum edges
+    int32_t n_mat, n_pbin, n_loss, n_scat, n_cells, gbits;
+    uint32_t nscat_magic;        // floor(2^32 / n_scat) + 1 for exact c / n_scat, c < 2^16
+    float loss_lo, loss_w, scat_lo, scat_w;
+};
+
+// Geometry: boxes split into z-slabs.  Slab s covers [slab_z[s], slab_z[s+1])
+// with slab_z[0] = -inf and slab_z[n_slab] = +inf; slab_mask[s] has bit b set
+// when box b spans the whole slab in z, so inside the slab only the x and y
+// ranges of those boxes need testing, lowest index first.
+struct DevGeom {
+    int32_t n_box, n_slab, n_mag;
+    const double *box4;          // [n_box][4] xlo, xhi, ylo, yhi
+    const int32_t *material;     // [n_box]
+    const float4 *bfield;        // [n_box] (bx, by, bz, 0)
+    const int32_t *magnet;       // [n_box]
+    const double *slab_z;        // [n_slab + 1]
+    const uint64_t *slab_mask;   // [n_slab]
+    double x_max, y_max, z_max;
+};
+
+struct DevField {
+    const float4 *map;           // [nz][ny][nx] (bx, by, bz, 0); nullptr = no map
+    int32_t nx, ny, nz;
+    double lo[3];
+    double inv_d[3];             // (n - 1) / (hi - lo)
+};
+
+// Byte offsets of the tables staged in LDS by every block.
+struct LdsLayout {
+    int32_t off_e2, off_tot, off_box4, off_mat, off_bf, off_mag, off_slabz, off_slabm;
+    int32_t bytes;
+    int32_t totals_in_lds;
+};
+
+struct DevRun {
+    double h;                    // step length
+    double pmin2;
+    int32_t max_steps;
+    uint32_t key0, key1;
+    int64_t n;                   // input muons
+    int64_t lanes;               // n_variants * n
+    const float *scales;         // [n_variants][n_mag] or nullptr
+    double *ckpt;                // [n_ckpt][6][lanes] or nullptr
+    float *tape;                 // [max_steps][4][lanes] or nullptr
+    int32_t *trace;
+    int64_t n_trace;
+    int32_t trace_steps;
+};
+
+struct DevIO {
+    const double *x, *y, *z, *px, *py, *pz;
+    const int8_t *q;
+    double *ox, *oy, *oz, *opx, *opy, *opz;
+    int32_t *status, *n_steps, *volume;
+};
+
+struct Tables {
+    DevHist hist;
+    DevGeom geom;
+    DevField field;
+    LdsLayout lds;
+};
+
+// Launchers implemented in mt_kernels.hip.
+hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,
+                        hipStream_t s);
+hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, int block,
+                             int grid, int compact_every, unsigned long long *queue,
+                             hipStream_t s);
+int persistent_blocks_per_cu(const Tables &T, int block);
+hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero,
+                              hipStream_t s);
+hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
+                          const double *g_out, double *g_in, double *gs_lane, void *scratch,
+                          int block, hipStream_t s);
+// Deterministic per-variant sums.  tally: (zmax count, hit count, sigmoid sum);
+// column sums: out[v][c] = sum over lanes of variant v of vals[c][lane].
+hipError_t launch_tally(const DevIO &io, int64_t n, int32_t n_variants, double z_det,
+                        double r_ap, double r_scale, double *partial, int32_t n_part_blocks,
+                        double *out, hipStream_t s);
+hipError_t launch_column_sums(const double *vals, int32_t n_cols, int64_t n, int32_t n_variants,
+                              double *partial, int32_t n_part_blocks, double *out, hipStream_t s);
+int64_t adjoint_scratch_bytes(const Tables &T, int64_t lanes);
+
+}  // namespace mt

@@ -1,0 +1,945 @@
+// HIP kernels of the histogram-sampling muon transport for gfx950 (MI355X).
+//
+// One lane carries one muon through the transport loop of Algorithm 1
+// (Section "Simulation").  Muon state (r, p) lives in FP64 registers for the
+// whole trajectory; the per-step arithmetic (kick, rotation, RK4 stages) is
+// FP32 and its increments are accumulated into the FP64 state.  Every
+// discrete decision (break test, box, momentum bin) is an FP64 compare, and
+// the histogram cell is drawn by an exact integer inverse CDF, so decisions
+// agree with a double-precision reference except at stated boundary ties.
+//
+// Build with -ffp-contract=off: every fused multiply-add is written out as
+// fmaf(), so the same source yields the same bits in every kernel that
+// inlines it (plain, persistent and the adjoint's re-forward).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mt_internal.h"
+
+namespace mt {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each forming
+// the 64-bit products of counter words 0 and 2 with the two multipliers,
+// the high halves xored with words 1 and 3 and the round key, the key then
+// advanced by the two Weyl increments.  The key is the same for every lane.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// Tables staged in LDS by every block.
+// ---------------------------------------------------------------------------
+struct Lds {
+    const double *e2;
+    const uint32_t *tot;
+    const double *box4;
+    const int32_t *mat;
+    const float4 *bf;
+    const int32_t *mag;
+    const double *slabz;
+    const uint64_t *slabm;
+};
+
+__device__ __forceinline__ Lds stage_tables(char *smem, const Tables &T) {
+    const LdsLayout &L = T.lds;
+    double *e2 = reinterpret_cast<double *>(smem + L.off_e2);
+    uint32_t *tot = reinterpret_cast<uint32_t *>(smem + L.off_tot);
+    double *box4 = reinterpret_cast<double *>(smem + L.off_box4);
+    int32_t *mat = reinterpret_cast<int32_t *>(smem + L.off_mat);
+    float4 *bf = reinterpret_cast<float4 *>(smem + L.off_bf);
+    int32_t *mag = reinterpret_cast<int32_t *>(smem + L.off_mag);
+    double *slabz = reinterpret_cast<double *>(smem + L.off_slabz);
+    uint64_t *slabm = reinterpret_cast<uint64_t *>(smem + L.off_slabm);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i <= T.hist.n_pbin; i += nt) e2[i] = T.hist.edges2[i];
+    if (L.totals_in_lds) {
+        const int nh = T.hist.n_mat * T.hist.n_pbin;
+        for (int i = tid; i < nh; i += nt) tot[i] = T.hist.totals[i];
+    }
+    for (int i = tid; i < 4 * T.geom.n_box; i += nt) box4[i] = T.geom.box4[i];
+    for (int i = tid; i < T.geom.n_box; i += nt) {
+        mat[i] = T.geom.material[i];
+        bf[i] = T.geom.bfield[i];
+        mag[i] = T.geom.magnet[i];
+    }
+    for (int i = tid; i <= T.geom.n_slab; i += nt) slabz[i] = T.geom.slab_z[i];
+    for (int i = tid; i < T.geom.n_slab; i += nt) slabm[i] = T.geom.slab_mask[i];
+    __syncthreads();
+    return Lds{e2, tot, box4, mat, bf, mag, slabz, slabm};
+}
+
+// ---------------------------------------------------------------------------
+// Lane state.
+// ---------------------------------------------------------------------------
+struct Lane {
+    double x, y, z, px, py, pz;
+    float q;
+    int32_t k, status, ibin, slab, var;
+    uint32_t jlo, jhi;
+    int64_t g;
+};
+
+__device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, const DevRun &R) {
+    int64_t var = 0, j = g;
+    if (R.lanes != R.n) {
+        var = g / R.n;
+        j = g - var * R.n;
+    }
+    L.x = io.x[j];
+    L.y = io.y[j];
+    L.z = io.z[j];
+    L.px = io.px[j];
+    L.py = io.py[j];
+    L.pz = io.pz[j];
+    const int qi = io.q[j];
+    L.q = (float)qi;
+    L.var = (int32_t)var;
+    L.jlo = (uint32_t)j;
+    L.jhi = (uint32_t)((uint64_t)j >> 32);
+    L.g = g;
+    L.k = 0;
+    L.ibin = -1;
+    L.slab = -1;
+    L.status = MT_ST_RUNNING;
+    const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
+    const bool ok = isfinite(L.x) && isfinite(L.y) && isfinite(L.z) && isfinite(p2) &&
+                    p2 > 0.0 && (qi == 1 || qi == -1);
+    if (!ok) L.status = MT_ST_INVALID;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry: z-slab, then the slab's candidate boxes in index order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_slab(const Lds &S, int n_slab, double z, int s) {
+    if (s < 0) {                       // largest s with slabz[s] <= z (slabz[0] = -inf)
+        int lo = 0, hi = n_slab - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.slabz[mid] <= z) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    while (s > 0 && z < S.slabz[s]) --s;
+    while (s < n_slab - 1 && z >= S.slabz[s + 1]) ++s;
+    return s;
+}
+
+__device__ __forceinline__ int find_box(const Lds &S, int s, double x, double y) {
+    uint64_t m = S.slabm[s];
+    while (m) {
+        const int b = __builtin_ctzll(m);
+        const double *bx = S.box4 + 4 * b;
+        if (bx[0] <= x && x < bx[1] && bx[2] <= y && y < bx[3]) return b;
+        m &= m - 1;
+    }
+    return -1;
+}
+
+// Momentum bin i with e_i^2 <= |p|^2 < e_{i+1}^2, clamped to [0, P-1]; the
+// previous step's bin is the starting guess.
+__device__ __forceinline__ int find_bin(const Lds &S, int P, double p2, int i) {
+    if (i < 0) {
+        int lo = 0, hi = P - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.e2[mid] <= p2) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    while (i > 0 && p2 < S.e2[i]) --i;
+    while (i < P - 1 && p2 >= S.e2[i + 1]) ++i;
+    return i;
+}
+
+// Exact inverse CDF: t = floor(w * T / 2^32), cell = smallest c with C[c] > t.
+// The guide entry of the word's top bits brackets c, so most draws need no
+// probe of C at all.
+__device__ __forceinline__ int sample_cell(const DevHist &H, const Lds &S, bool tot_lds, int h,
+                                           uint32_t w0) {
+    const uint32_t T = tot_lds ? S.tot[h] : H.totals[h];
+    const uint32_t t = __umulhi(w0, T);
+    int lo = 0, hi = H.n_cells - 1;
+    if (H.guide != nullptr) {
+        const uint32_t pk = H.guide[((size_t)h << H.gbits) | (w0 >> (32 - H.gbits))];
+        lo = (int)(pk & 0xFFFFu);
+        hi = (int)(pk >> 16);
+    }
+    const uint32_t *C = H.cdf + (size_t)h * H.n_cells;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (C[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Kick: p <- p + R(p_hat) (|p| u), u = (tau cos phi, tau sin phi, -f), with the
+// division-free Rodrigues form R v = c v + a x v + (a.v) a / (1 + c),
+// a = z x p_hat = (-ny, nx, 0), c = nz (equal to Eq. (2) with k = a/|a|).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void kick(Lane &L, double p2, float ux, float uy, float uz) {
+    const float p2f = (float)p2;
+    const float rinv = __builtin_amdgcn_rsqf(p2f);
+    const float pm = p2f * rinv;
+    const float nx = (float)L.px * rinv, ny = (float)L.py * rinv, nz = (float)L.pz * rinv;
+    const float dx = pm * ux, dy = pm * uy, dz = pm * uz;
+    const float opc = 1.0f + nz;
+    float rx, ry, rz;
+    if (opc > 0.0f) {
+        const float adot = fmaf(nx, dy, -ny * dx);
+        const float coef = adot * __builtin_amdgcn_rcpf(opc);
+        rx = fmaf(nz, dx, fmaf(nx, dz, -coef * ny));
+        ry = fmaf(nz, dy, fmaf(ny, dz, coef * nx));
+        rz = fmaf(nz, dz, -fmaf(nx, dx, ny * dy));
+    } else {                           // exactly backwards: rotation by pi about x
+        rx = dx;
+        ry = -dy;
+        rz = -dz;
+    }
+    L.px += (double)rx;
+    L.py += (double)ry;
+    L.pz += (double)rz;
+}
+
+// ---------------------------------------------------------------------------
+// Field at the start of the step: scaled per-box field + trilinear map.
+// ---------------------------------------------------------------------------
+struct Corner8 {
+    float4 c000, c100, c010, c110, c001, c101, c011, c111;
+    float fx, fy, fz;
+};
+
+__device__ __forceinline__ bool map_cell(const DevField &F, double x, double y, double z,
+                                         Corner8 &c) {
+    const double u = (x - F.lo[0]) * F.inv_d[0];
+    const double v = (y - F.lo[1]) * F.inv_d[1];
+    const double w = (z - F.lo[2]) * F.inv_d[2];
+    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
+          w >= 0.0 && w <= (double)(F.nz - 1)))
+        return false;
+    const int i = min((int)u, F.nx - 2), j = min((int)v, F.ny - 2), k = min((int)w, F.nz - 2);
+    c.fx = (float)(u - (double)i);
+    c.fy = (float)(v - (double)j);
+    c.fz = (float)(w - (double)k);
+    const size_t sy = (size_t)F.nx, sz = (size_t)F.nx * F.ny;
+    const float4 *b = F.map + (size_t)k * sz + (size_t)j * sy + i;
+    c.c000 = b[0];
+    c.c100 = b[1];
+    c.c010 = b[sy];
+    c.c110 = b[sy + 1];
+    c.c001 = b[sz];
+    c.c101 = b[sz + 1];
+    c.c011 = b[sz + sy];
+    c.c111 = b[sz + sy + 1];
+    return true;
+}
+
+__device__ __forceinline__ float lerp1(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+__device__ __forceinline__ float3 trilerp(const Corner8 &c) {
+    float3 r;
+    r.x = lerp1(lerp1(lerp1(c.c000.x, c.c100.x, c.fx), lerp1(c.c010.x, c.c110.x, c.fx), c.fy),
+                lerp1(lerp1(c.c001.x, c.c101.x, c.fx), lerp1(c.c011.x, c.c111.x, c.fx), c.fy), c.fz);
+    r.y = lerp1(lerp1(lerp1(c.c000.y, c.c100.y, c.fx), lerp1(c.c010.y, c.c110.y, c.fx), c.fy),
+                lerp1(lerp1(c.c001.y, c.c101.y, c.fx), lerp1(c.c011.y, c.c111.y, c.fx), c.fy), c.fz);
+    r.z = lerp1(lerp1(lerp1(c.c000.z, c.c100.z, c.fx), lerp1(c.c010.z, c.c110.z, c.fx), c.fy),
+                lerp1(lerp1(c.c001.z, c.c101.z, c.fx), lerp1(c.c011.z, c.c111.z, c.fx), c.fy), c.fz);
+    return r;
+}
+
+template <bool MAP>
+__device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const DevRun &R, int vol,
+                                           int var, double x, double y, double z) {
+    float3 B = make_float3(0.f, 0.f, 0.f);
+    if (vol >= 0) {
+        const float4 b = S.bf[vol];
+        const int m = S.mag[vol];
+        const float s = (m >= 0 && R.scales != nullptr) ? R.scales[var * T.geom.n_mag + m] : 1.0f;
+        B = make_float3(b.x * s, b.y * s, b.z * s);
+    }
+    if (MAP) {
+        Corner8 c;
+        if (map_cell(T.field, x, y, z, c)) {
+            const float3 m = trilerp(c);
+            B.x += m.x;
+            B.y += m.y;
+            B.z += m.z;
+        }
+    }
+    return B;
+}
+
+// ---------------------------------------------------------------------------
+// RK4 over arc length with B frozen: dr/ds = p/|p|, dp/ds = kappa q (p/|p|) x B.
+// FP32 stages, increments added to the FP64 state.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z),
+                       fmaf(a.x, b.y, -a.y * b.x));
+}
+
+__device__ __forceinline__ float norm2(float3 a) { return fmaf(a.x, a.x, fmaf(a.y, a.y, a.z * a.z)); }
+
+__device__ __forceinline__ float3 axpy(float a, float3 x, float3 y) {
+    return make_float3(fmaf(a, x.x, y.x), fmaf(a, x.y, y.y), fmaf(a, x.z, y.z));
+}
+
+__device__ __forceinline__ float3 scale3(float a, float3 x) {
+    return make_float3(a * x.x, a * x.y, a * x.z);
+}
+
+__device__ __forceinline__ float3 add3(float3 a, float3 b) {
+    return make_float3(a.x + b.x, a.y + b.y, a.z + b.z);
+}
+
+struct StepConst {
+    float h, h2, h6, h3;   // d, d/2, d/6, d/3
+};
+
+__device__ __forceinline__ void rk4(Lane &L, float3 B, const StepConst &c) {
+    const float3 a0 = make_float3((float)L.px, (float)L.py, (float)L.pz);
+    const float r0 = __builtin_amdgcn_rsqf(norm2(a0));
+    const float3 n0 = scale3(r0, a0);
+    if (B.x == 0.0f && B.y == 0.0f && B.z == 0.0f) {
+        L.x += (double)(c.h * n0.x);
+        L.y += (double)(c.h * n0.y);
+        L.z += (double)(c.h * n0.z);
+        return;
+    }
+    const float kq = (float)kKappa * L.q;
+    const float3 cb = scale3(kq, B);
+    const float3 k1 = cross3(n0, cb);
+    const float3 a1 = axpy(c.h2, k1, a0);
+    const float3 n1 = scale3(__builtin_amdgcn_rsqf(norm2(a1)), a1);
+    const float3 k2 = cross3(n1, cb);
+    const float3 a2 = axpy(c.h2, k2, a0);
+    const float3 n2 = scale3(__builtin_amdgcn_rsqf(norm2(a2)), a2);
+    const float3 k3 = cross3(n2, cb);
+    const float3 a3 = axpy(c.h, k3, a0);
+    const float3 n3 = scale3(__builtin_amdgcn_rsqf(norm2(a3)), a3);
+    const float3 k4 = cross3(n3, cb);
+    // h/6 (v1 + 2 v2 + 2 v3 + v4)
+    const float drx = c.h6 * (fmaf(2.0f, n1.x + n2.x, n0.x) + n3.x);
+    const float dry = c.h6 * (fmaf(2.0f, n1.y + n2.y, n0.y) + n3.y);
+    const float drz = c.h6 * (fmaf(2.0f, n1.z + n2.z, n0.z) + n3.z);
+    const float dpx = c.h6 * (fmaf(2.0f, k2.x + k3.x, k1.x) + k4.x);
+    const float dpy = c.h6 * (fmaf(2.0f, k2.y + k3.y, k1.y) + k4.y);
+    const float dpz = c.h6 * (fmaf(2.0f, k2.z + k3.z, k1.z) + k4.z);
+    L.x += (double)drx;
+    L.y += (double)dry;
+    L.z += (double)drz;
+    L.px += (double)dpx;
+    L.py += (double)dpy;
+    L.pz += (double)dpz;
+}
+
+// ---------------------------------------------------------------------------
+// One iteration of the transport loop.  Returns false (with L.status set)
+// when a break condition holds at the top of the iteration.
+// ---------------------------------------------------------------------------
+template <bool MAP, bool TAPE>
+__device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, const DevRun &R,
+                                        const StepConst &sc) {
+    const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
+    int st = MT_ST_RUNNING;
+    if (p2 < R.pmin2) st = MT_ST_PMIN;
+    else if (L.z >= T.geom.z_max) st = MT_ST_ZMAX;
+    else if (fabs(L.x) >= T.geom.x_max) st = MT_ST_XMAX;
+    else if (fabs(L.y) >= T.geom.y_max) st = MT_ST_YMAX;
+    else if (L.k >= R.max_steps) st = MT_ST_MAXSTEPS;
+    if (st != MT_ST_RUNNING) {
+        L.status = st;
+        return false;
+    }
+    L.slab = find_slab(S, T.geom.n_slab, L.z, L.slab);
+    const int vol = find_box(S, L.slab, L.x, L.y);
+    const int mat = vol >= 0 ? S.mat[vol] : -1;
+    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+    int cell = -1;
+    if (mat >= 0) {
+        L.ibin = find_bin(S, T.hist.n_pbin, p2, L.ibin);
+        const uint4 w = philox10(L.jlo, L.jhi, (uint32_t)L.k, 0u, R.key0, R.key1);
+        const int h = mat * T.hist.n_pbin + L.ibin;
+        cell = sample_cell(T.hist, S, T.lds.totals_in_lds != 0, h, w.x);
+        const int il = (int)__umulhi((uint32_t)cell, T.hist.nscat_magic);
+        const int is = cell - il * T.hist.n_scat;
+        const float v1 = (float)(w.y >> 8) * 0x1p-24f;
+        const float v2 = (float)(w.z >> 8) * 0x1p-24f;
+        const float v3 = (float)(w.w >> 8) * 0x1p-24f;
+        const float f = fmaf((float)il + v1, T.hist.loss_w, T.hist.loss_lo);
+        const float tau = fmaf((float)is + v2, T.hist.scat_w, T.hist.scat_lo);
+        // v_sin_f32 / v_cos_f32 take their argument in revolutions: sin(2 pi v3).
+        const float sn = __builtin_amdgcn_sinf(v3);
+        const float cs = __builtin_amdgcn_cosf(v3);
+        ux = tau * cs;
+        uy = tau * sn;
+        uz = -f;
+        kick(L, p2, ux, uy, uz);
+    }
+    if (TAPE) {
+        float *tp = R.tape + (size_t)L.k * 4 * R.lanes + L.g;
+        tp[0] = ux;
+        tp[R.lanes] = uy;
+        tp[2 * R.lanes] = uz;
+        tp[3 * R.lanes] = __int_as_float(vol);
+    }
+    if (L.g < R.n_trace && L.k < R.trace_steps) {
+        int32_t *tr = R.trace + ((size_t)L.g * R.trace_steps + L.k) * 3;
+        tr[0] = vol;
+        tr[1] = mat >= 0 ? L.ibin : -1;
+        tr[2] = cell;
+    }
+    const float3 B = field_at<MAP>(T, S, R, vol, L.var, L.x, L.y, L.z);
+    rk4(L, B, sc);
+    ++L.k;
+    return true;
+}
+
+__device__ __forceinline__ StepConst step_const(const DevRun &R) {
+    StepConst c;
+    c.h = (float)R.h;
+    c.h2 = (float)(0.5 * R.h);
+    c.h6 = (float)(R.h / 6.0);
+    c.h3 = (float)(R.h / 3.0);
+    return c;
+}
+
+__device__ __forceinline__ void store_lane(const Lane &L, const Tables &T, const Lds &S,
+                                           const DevIO &io) {
+    const int64_t g = L.g;
+    io.ox[g] = L.x;
+    io.oy[g] = L.y;
+    io.oz[g] = L.z;
+    io.opx[g] = L.px;
+    io.opy[g] = L.py;
+    io.opz[g] = L.pz;
+    io.status[g] = L.status;
+    io.n_steps[g] = L.k;
+    int vol = -1;
+    if (L.status != MT_ST_INVALID) {
+        const int s = find_slab(S, T.geom.n_slab, L.z, L.slab);
+        vol = find_box(S, s, L.x, L.y);
+    }
+    io.volume[g] = vol;
+}
+
+__device__ __forceinline__ void write_ckpt(const Lane &L, const DevRun &R) {
+    double *c = R.ckpt + (size_t)(L.k / kCkptEvery) * 6 * R.lanes + L.g;
+    c[0] = L.x;
+    c[R.lanes] = L.y;
+    c[2 * R.lanes] = L.z;
+    c[3 * R.lanes] = L.px;
+    c[4 * R.lanes] = L.py;
+    c[5 * R.lanes] = L.pz;
+}
+
+// ---------------------------------------------------------------------------
+// Plain form: one lane per (variant, muon) until it stops.
+// ---------------------------------------------------------------------------
+template <bool MAP, bool CKPT>
+__global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = stage_tables(smem, T);
+    const StepConst sc = step_const(R);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= R.lanes) return;
+    Lane L;
+    load_lane(L, g, io, R);
+    if (L.status == MT_ST_RUNNING) {
+        for (;;) {
+            if (CKPT && (L.k % kCkptEvery) == 0 && L.k < R.max_steps) write_ckpt(L, R);
+            if (!advance<MAP, CKPT>(L, T, S, R, sc)) break;
+        }
+    }
+    store_lane(L, T, S, io);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form: a resident grid pulls muons from an atomic queue.  Every
+// `compact` steps each wave writes out its finished muons and refills those
+// lanes with the next queue entries (ballot + prefix count), so waves stay
+// full while trajectory lengths differ.  Results are bit-identical to the
+// plain form because the random stream is keyed by (muon, step), not by lane.
+// A wave exits once the queue is exhausted and all of its lanes are idle.
+// ---------------------------------------------------------------------------
+template <bool MAP>
+__global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO io, int compact,
+                                                     unsigned long long *queue) {
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = stage_tables(smem, T);
+    const StepConst sc = step_const(R);
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    Lane L;
+    L.status = MT_ST_INVALID;
+    bool active = false, exhausted = false;
+    for (;;) {
+        const uint64_t empty = __ballot(!active);
+        if (!exhausted && empty != 0ull) {
+            const uint32_t n_empty = (uint32_t)__popcll(empty);
+            unsigned long long base = 0ull;
+            if (lane == 0) base = atomicAdd(queue, (unsigned long long)n_empty);
+            base = __shfl(base, 0);
+            if (!active) {
+                const unsigned long long g = base + (unsigned long long)__popcll(empty & below);
+                if (g < (unsigned long long)R.lanes) {
+                    load_lane(L, (int64_t)g, io, R);
+                    if (L.status == MT_ST_RUNNING) active = true;
+                    else store_lane(L, T, S, io);
+                }
+            }
+            if (base + n_empty >= (unsigned long long)R.lanes) exhausted = true;
+        }
+        if (__ballot(active) == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        for (int c = 0; c < compact; ++c) {
+            if (active && !advance<MAP, false>(L, T, S, R, sc)) {
+                store_lane(L, T, S, io);
+                active = false;
+            }
+        }
+    }
+}
+
+__global__ void k_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *queue = 0ull;
+    if (i < n_zero) zero[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (pathwise; sampled kicks, decisions and step count held fixed).
+//
+// Forward step, in the order of the plain kernel:
+//   a0 = p + |p| R(p_hat) u                          (kick, if in material)
+//   k_i = c n_i x B, n_i = a_i/|a_i|, c = kappa q     (RK4 stages)
+//   a1 = a0 + h/2 k1, a2 = a0 + h/2 k2, a3 = a0 + h k3
+//   r' = r + h/6 (n0 + 2 n1 + 2 n2 + n3),  p' = a0 + h/6 (k1 + 2 k2 + 2 k3 + k4)
+// The reverse sweep maps (lr', lp') to (lr, lp) and accumulates lB . dB/ds
+// into the magnet's scale gradient.  The identity part of every Jacobian is
+// applied in FP64; the O(h) and O(f, tau) corrections are formed in FP32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 unit_jt(float3 n, float rinv, float3 l) {
+    // (I - n n^T) l / |a|
+    const float d = fmaf(n.x, l.x, fmaf(n.y, l.y, n.z * l.z));
+    return make_float3(rinv * fmaf(-d, n.x, l.x), rinv * fmaf(-d, n.y, l.y),
+                       rinv * fmaf(-d, n.z, l.z));
+}
+
+__device__ __forceinline__ float dot3(float3 a, float3 b) {
+    return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
+}
+
+// Post-kick momentum from an FP32 pre-kick momentum (same algebra as kick()).
+__device__ __forceinline__ float3 kick_f32(float3 p, float3 u) {
+    const float p2f = norm2(p);
+    const float rinv = __builtin_amdgcn_rsqf(p2f);
+    const float pm = p2f * rinv;
+    const float nx = p.x * rinv, ny = p.y * rinv, nz = p.z * rinv;
+    const float dx = pm * u.x, dy = pm * u.y, dz = pm * u.z;
+    const float opc = 1.0f + nz;
+    float rx, ry, rz;
+    if (opc > 0.0f) {
+        const float adot = fmaf(nx, dy, -ny * dx);
+        const float coef = adot * __builtin_amdgcn_rcpf(opc);
+        rx = fmaf(nz, dx, fmaf(nx, dz, -coef * ny));
+        ry = fmaf(nz, dy, fmaf(ny, dz, coef * nx));
+        rz = fmaf(nz, dz, -fmaf(nx, dx, ny * dy));
+    } else {
+        rx = dx;
+        ry = -dy;
+        rz = -dz;
+    }
+    return make_float3(p.x + rx, p.y + ry, p.z + rz);
+}
+
+// Gradient of l . g_u(p) with g_u(p) = p_z u + A x u + (A.u) A / (|p| + p_z),
+// A = (-p_y, p_x, 0): the kick is p -> p + g_u(p).
+__device__ __forceinline__ float3 kick_adjoint_corr(float3 p, float3 u, float3 l) {
+    const float P = sqrtf(norm2(p));
+    const float D = P + p.z;
+    const float alpha = fmaf(-p.y, u.x, p.x * u.y);
+    const float beta = fmaf(-p.y, l.x, p.x * l.y);
+    const float3 v = cross3(u, l);
+    const float invD = 1.0f / D;
+    const float Q = alpha * beta * invD;
+    const float invP = 1.0f / P;
+    float3 g;
+    g.x = v.y + (beta * u.y + alpha * l.y) * invD - Q * invD * (p.x * invP);
+    g.y = -v.x + (-beta * u.x - alpha * l.x) * invD - Q * invD * (p.y * invP);
+    g.z = dot3(l, u) - Q * invD * (p.z * invP + 1.0f);
+    return g;
+}
+
+// d(trilinear)/dr contracted with lB.
+__device__ __forceinline__ float3 map_grad_t(const DevField &F, const Corner8 &c, float3 lB) {
+    const float gx = 1.0f - c.fx, gy = 1.0f - c.fy, gz = 1.0f - c.fz;
+    auto dot4 = [&](float4 a) { return fmaf(lB.x, a.x, fmaf(lB.y, a.y, lB.z * a.z)); };
+    const float v000 = dot4(c.c000), v100 = dot4(c.c100), v010 = dot4(c.c010), v110 = dot4(c.c110);
+    const float v001 = dot4(c.c001), v101 = dot4(c.c101), v011 = dot4(c.c011), v111 = dot4(c.c111);
+    const float dx = gy * gz * (v100 - v000) + c.fy * gz * (v110 - v010) +
+                     gy * c.fz * (v101 - v001) + c.fy * c.fz * (v111 - v011);
+    const float dy = gx * gz * (v010 - v000) + c.fx * gz * (v110 - v100) +
+                     gx * c.fz * (v011 - v001) + c.fx * c.fz * (v111 - v101);
+    const float dz = gx * gy * (v001 - v000) + c.fx * gy * (v101 - v100) +
+                     gx * c.fy * (v011 - v010) + c.fx * c.fy * (v111 - v110);
+    return make_float3(dx * (float)F.inv_d[0], dy * (float)F.inv_d[1], dz * (float)F.inv_d[2]);
+}
+
+template <bool MAP>
+__global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
+                                                 double *g_in, double *gs_lane, char *scratch) {
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = stage_tables(smem, T);
+    const StepConst sc = step_const(R);
+    double *sgs = reinterpret_cast<double *>(smem + ((T.lds.bytes + 15) & ~15)) + threadIdx.x;
+    const int bd = blockDim.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= R.lanes) return;
+    const int64_t lanes = R.lanes;
+    const int n_mag = T.geom.n_mag;
+    for (int m = 0; m < n_mag; ++m) sgs[m * bd] = 0.0;
+    double lr[3], lp[3];
+    for (int a = 0; a < 3; ++a) {
+        lr[a] = g_out[a * lanes + g];
+        lp[a] = g_out[(3 + a) * lanes + g];
+    }
+    const int ns = io.n_steps[g];
+    const int status = io.status[g];
+    int var = 0;
+    if (R.lanes != R.n) var = (int)(g / R.n);
+    const float q = (float)io.q[g - (int64_t)var * R.n];
+    const float kq = (float)kKappa * q;
+    float *hp = reinterpret_cast<float *>(scratch);
+    double *hr = reinterpret_cast<double *>(scratch + (size_t)kCkptEvery * 3 * sizeof(float) * lanes);
+
+    if (status != MT_ST_INVALID && ns > 0) {
+        for (int seg = (ns - 1) / kCkptEvery; seg >= 0; --seg) {
+            const int k0 = seg * kCkptEvery;
+            const int k1 = min(k0 + kCkptEvery, ns);
+            Lane L;
+            const double *c = R.ckpt + (size_t)seg * 6 * lanes + g;
+            L.x = c[0];
+            L.y = c[lanes];
+            L.z = c[2 * lanes];
+            L.px = c[3 * lanes];
+            L.py = c[4 * lanes];
+            L.pz = c[5 * lanes];
+            L.q = q;
+            // Re-forward the segment from its checkpoint with the recorded
+            // kicks and volumes; the arithmetic is that of advance().
+            for (int k = k0; k < k1; ++k) {
+                float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
+                h[0] = (float)L.px;
+                h[lanes] = (float)L.py;
+                h[2 * lanes] = (float)L.pz;
+                if (MAP) {
+                    double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
+                    hh[0] = L.x;
+                    hh[lanes] = L.y;
+                    hh[2 * lanes] = L.z;
+                }
+                const float *tp = R.tape + (size_t)k * 4 * lanes + g;
+                const int vol = __float_as_int(tp[3 * lanes]);
+                const int mat = vol >= 0 ? S.mat[vol] : -1;
+                if (mat >= 0) {
+                    const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
+                    kick(L, p2, tp[0], tp[lanes], tp[2 * lanes]);
+                }
+                const float3 B = field_at<MAP>(T, S, R, vol, var, L.x, L.y, L.z);
+                rk4(L, B, sc);
+            }
+            // Reverse sweep.
+            for (int k = k1 - 1; k >= k0; --k) {
+                const float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
+                const float3 p0 = make_float3(h[0], h[lanes], h[2 * lanes]);
+                const float *tp = R.tape + (size_t)k * 4 * lanes + g;
+                const int vol = __float_as_int(tp[3 * lanes]);
+                const int mat = vol >= 0 ? S.mat[vol] : -1;
+                const float3 u = make_float3(tp[0], tp[lanes], tp[2 * lanes]);
+                const float3 a0 = mat >= 0 ? kick_f32(p0, u) : p0;
+                double rx = 0.0, ry = 0.0, rz = 0.0;
+                if (MAP) {
+                    const double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
+                    rx = hh[0];
+                    ry = hh[lanes];
+                    rz = hh[2 * lanes];
+                }
+                const float3 B = field_at<MAP>(T, S, R, vol, var, rx, ry, rz);
+                const float3 Lr = make_float3((float)lr[0], (float)lr[1], (float)lr[2]);
+                const float3 Lp = make_float3((float)lp[0], (float)lp[1], (float)lp[2]);
+                // RK4 stages of the step (the straight-line shortcut of the
+                // forward pass equals them at B = 0, so one form serves both).
+                const float3 cb = scale3(kq, B);
+                const float r0 = __builtin_amdgcn_rsqf(norm2(a0));
+                const float3 n0 = scale3(r0, a0);
+                const float3 k1v = cross3(n0, cb);
+                const float3 a1 = axpy(sc.h2, k1v, a0);
+                const float r1 = __builtin_amdgcn_rsqf(norm2(a1));
+                const float3 n1 = scale3(r1, a1);
+                const float3 k2v = cross3(n1, cb);
+                const float3 a2 = axpy(sc.h2, k2v, a0);
+                const float r2 = __builtin_amdgcn_rsqf(norm2(a2));
+                const float3 n2 = scale3(r2, a2);
+                const float3 k3v = cross3(n2, cb);
+                const float3 a3 = axpy(sc.h, k3v, a0);
+                const float r3 = __builtin_amdgcn_rsqf(norm2(a3));
+                const float3 n3 = scale3(r3, a3);
+                // Reverse through k4 = c n3 x B, a3 = a0 + h k3, ..., k1 = c n0 x B.
+                float3 lk3 = scale3(sc.h3, Lp);
+                float3 lk2 = scale3(sc.h3, Lp);
+                float3 lk1 = scale3(sc.h6, Lp);
+                const float3 lk4 = scale3(sc.h6, Lp);
+                float3 lBc = cross3(lk4, n3);
+                float3 la = unit_jt(n3, r3, axpy(sc.h6, Lr, cross3(cb, lk4)));
+                float3 corr = la;
+                lk3 = axpy(sc.h, la, lk3);
+                lBc = add3(lBc, cross3(lk3, n2));
+                la = unit_jt(n2, r2, axpy(sc.h3, Lr, cross3(cb, lk3)));
+                corr = add3(corr, la);
+                lk2 = axpy(sc.h2, la, lk2);
+                lBc = add3(lBc, cross3(lk2, n1));
+                la = unit_jt(n1, r1, axpy(sc.h3, Lr, cross3(cb, lk2)));
+                corr = add3(corr, la);
+                lk1 = axpy(sc.h2, la, lk1);
+                lBc = add3(lBc, cross3(lk1, n0));
+                la = unit_jt(n0, r0, axpy(sc.h6, Lr, cross3(cb, lk1)));
+                corr = add3(corr, la);
+                const float3 lB = scale3(kq, lBc);
+                // lambda of a0 (post-kick momentum)
+                double la0[3] = {lp[0] + (double)corr.x, lp[1] + (double)corr.y,
+                                 lp[2] + (double)corr.z};
+                if (mat >= 0) {
+                    const float3 l = make_float3((float)la0[0], (float)la0[1], (float)la0[2]);
+                    const float3 kc = kick_adjoint_corr(p0, u, l);
+                    la0[0] += (double)kc.x;
+                    la0[1] += (double)kc.y;
+                    la0[2] += (double)kc.z;
+                }
+                lp[0] = la0[0];
+                lp[1] = la0[1];
+                lp[2] = la0[2];
+                if (vol >= 0) {
+                    const int m = S.mag[vol];
+                    if (m >= 0) {
+                        const float4 b = S.bf[vol];
+                        sgs[m * bd] += (double)fmaf(lB.x, b.x, fmaf(lB.y, b.y, lB.z * b.z));
+                    }
+                }
+                if (MAP) {
+                    Corner8 cc;
+                    if (map_cell(T.field, rx, ry, rz, cc)) {
+                        const float3 gr = map_grad_t(T.field, cc, lB);
+                        lr[0] += (double)gr.x;
+                        lr[1] += (double)gr.y;
+                        lr[2] += (double)gr.z;
+                    }
+                }
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        g_in[a * lanes + g] = lr[a];
+        g_in[(3 + a) * lanes + g] = lp[a];
+    }
+    for (int m = 0; m < n_mag; ++m) gs_lane[(size_t)m * lanes + g] = sgs[m * bd];
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic per-variant sums (fixed chunking and fixed tree order).
+// ---------------------------------------------------------------------------
+constexpr int kRedBlock = 256;
+
+template <int NC, typename F>
+__device__ __forceinline__ void block_partial(F &&term, int64_t begin, int64_t end,
+                                              double *partial_out) {
+    __shared__ double red[NC][kRedBlock];
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int64_t i = begin + threadIdx.x; i < end; i += kRedBlock) term(i, acc);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) partial_out[c] = red[c][0];
+    }
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_tally_pass1(DevIO io, int64_t n, double z_det,
+                                                           double r_ap, double r_scale,
+                                                           double *partial) {
+    const int v = blockIdx.y, b = blockIdx.x, nb = gridDim.x;
+    const int64_t chunk = (n + nb - 1) / nb;
+    const int64_t base = (int64_t)v * n;
+    const int64_t begin = base + min((int64_t)b * chunk, n);
+    const int64_t end = base + min((int64_t)(b + 1) * chunk, n);
+    auto term = [&](int64_t i, double *acc) {
+        if (io.status[i] == MT_ST_ZMAX) {
+            const double dz = z_det - io.oz[i];
+            const double xd = io.ox[i] + dz * io.opx[i] / io.opz[i];
+            const double yd = io.oy[i] + dz * io.opy[i] / io.opz[i];
+            const double r = sqrt(xd * xd + yd * yd);
+            acc[0] += 1.0;
+            acc[1] += (r < r_ap) ? 1.0 : 0.0;
+            acc[2] += 1.0 / (1.0 + exp(-(r_ap - r) / r_scale));
+        }
+    };
+    block_partial<3>(term, begin, end, partial + ((size_t)v * nb + b) * 3);
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_colsum_pass1(const double *vals, int n_cols,
+                                                            int64_t n, int64_t lanes,
+                                                            double *partial) {
+    const int v = blockIdx.y, b = blockIdx.x, nb = gridDim.x;
+    const int64_t chunk = (n + nb - 1) / nb;
+    const int64_t base = (int64_t)v * n;
+    const int64_t begin = base + min((int64_t)b * chunk, n);
+    const int64_t end = base + min((int64_t)(b + 1) * chunk, n);
+    for (int c0 = 0; c0 < n_cols; c0 += 4) {
+        const double *col = vals + (size_t)c0 * lanes;
+        const int nc = min(4, n_cols - c0);
+        auto term = [&](int64_t i, double *acc) {
+            for (int c = 0; c < nc; ++c) acc[c] += col[(size_t)c * lanes + i];
+        };
+        double tmp[4];
+        block_partial<4>(term, begin, end, tmp);
+        if (threadIdx.x == 0)
+            for (int c = 0; c < nc; ++c)
+                partial[((size_t)v * nb + b) * n_cols + c0 + c] = tmp[c];
+        __syncthreads();
+    }
+}
+
+// out[v][c] = sum over b of partial[v][b][c], in order of b.
+__global__ void k_pass2(const double *partial, int nb, int n_cols, int n_variants, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_variants * n_cols) return;
+    const int v = i / n_cols, c = i - v * n_cols;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[((size_t)v * nb + b) * n_cols + c];
+    out[i] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,
+                        hipStream_t s) {
+    if (R.lanes == 0) return hipSuccess;
+    const int64_t grid = (R.lanes + block - 1) / block;
+    const bool map = T.field.map != nullptr;
+    const bool ck = R.ckpt != nullptr;
+    const size_t shm = (size_t)T.lds.bytes;
+    if (map && ck) hipLaunchKernelGGL((k_plain<true, true>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
+    else if (map) hipLaunchKernelGGL((k_plain<true, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
+    else if (ck) hipLaunchKernelGGL((k_plain<false, true>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
+    else hipLaunchKernelGGL((k_plain<false, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
+    return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(const Tables &T, int block) {
+    int n = 0;
+    const bool map = T.field.map != nullptr;
+    hipError_t e = map ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &n, reinterpret_cast<const void *>(k_persistent<true>), block, T.lds.bytes)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &n, reinterpret_cast<const void *>(k_persistent<false>), block, T.lds.bytes);
+    if (e != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, int block,
+                             int grid, int compact_every, unsigned long long *queue,
+                             hipStream_t s) {
+    if (R.lanes == 0) return hipSuccess;
+    const size_t shm = (size_t)T.lds.bytes;
+    if (T.field.map != nullptr)
+        hipLaunchKernelGGL((k_persistent<true>), dim3(grid), dim3(block), shm, s, T, R, io, compact_every, queue);
+    else
+        hipLaunchKernelGGL((k_persistent<false>), dim3(grid), dim3(block), shm, s, T, R, io, compact_every, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero,
+                              hipStream_t s) {
+    const int64_t n = n_zero > 1 ? n_zero : 1;
+    hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, queue,
+                       zero, n_zero);
+    return hipGetLastError();
+}
+
+int64_t adjoint_scratch_bytes(const Tables &T, int64_t lanes) {
+    int64_t b = (int64_t)kCkptEvery * 3 * sizeof(float) * lanes;
+    if (T.field.map != nullptr) b += (int64_t)kCkptEvery * 3 * sizeof(double) * lanes;
+    return b;
+}
+
+hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
+                          const double *g_out, double *g_in, double *gs_lane, void *scratch,
+                          int block, hipStream_t s) {
+    if (R.lanes == 0) return hipSuccess;
+    const int64_t grid = (R.lanes + block - 1) / block;
+    const size_t shm = (size_t)((T.lds.bytes + 15) & ~15) +
+                       (size_t)T.geom.n_mag * block * sizeof(double);
+    char *sc = reinterpret_cast<char *>(scratch);
+    if (T.field.map != nullptr)
+        hipLaunchKernelGGL((k_adjoint<true>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
+    else
+        hipLaunchKernelGGL((k_adjoint<false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_tally(const DevIO &io, int64_t n, int32_t n_variants, double z_det,
+                        double r_ap, double r_scale, double *partial, int32_t n_part_blocks,
+                        double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_tally_pass1, dim3(n_part_blocks, n_variants), dim3(kRedBlock), 0, s, io,
+                       n, z_det, r_ap, r_scale, partial);
+    const int nout = n_variants * 3;
+    hipLaunchKernelGGL(k_pass2, dim3((nout + 127) / 128), dim3(128), 0, s, partial, n_part_blocks,
+                       3, n_variants, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_column_sums(const double *vals, int32_t n_cols, int64_t n, int32_t n_variants,
+                              double *partial, int32_t n_part_blocks, double *out, hipStream_t s) {
+    if (n_cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colsum_pass1, dim3(n_part_blocks, n_variants), dim3(kRedBlock), 0, s,
+                       vals, n_cols, n, n * n_variants, partial);
+    const int nout = n_variants * n_cols;
+    hipLaunchKernelGGL(k_pass2, dim3((nout + 127) / 128), dim3(128), 0, s, partial, n_part_blocks,
+                       n_cols, n_variants, out);
+    return hipGetLastError();
+}
+
+}  // namespace mt
