@@ -68,7 +68,8 @@ class _Out(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "px", "py", "pz",
                                           "status", "n_steps", "volume",
                                           "margin_pos", "margin_p", "trace")] + \
-               [("trace_steps", C.c_int32), ("kicks", C.c_void_p), ("kick_steps", C.c_int32)]
+               [("trace_steps", C.c_int32), ("kicks", C.c_void_p), ("kick_steps", C.c_int32),
+                ("step_margin", C.c_void_p)]
 
 
 def lib():
@@ -153,6 +154,7 @@ class Result:
     margin_p: np.ndarray     # float64 [n] (relative)
     trace: Optional[np.ndarray] = None   # int32 [n][trace_steps][3]
     kicks: Optional[np.ndarray] = None   # float32 [n][kick_steps][3]
+    step_margin: Optional[np.ndarray] = None   # float64 [n][trace_steps+1][2]
 
 
 def propagate(wl, idx=None, variant=None, muons=None, scales=None, seed=None,
@@ -188,14 +190,15 @@ def propagate(wl, idx=None, variant=None, muons=None, scales=None, seed=None,
     mp = np.zeros(n, np.float64)
     trace = np.full((n, trace_steps, 3), -2, np.int32) if trace_steps > 0 else None
     kicks = np.zeros((n, kick_steps, 3), np.float32) if kick_steps > 0 else None
+    smarg = np.full((n, trace_steps + 1, 2), np.inf) if trace_steps > 0 else None
     I = _In(*[st[a].ctypes.data for a in range(6)], q.ctypes.data, idx.ctypes.data, _ptr(var))
     O = _Out(*[out_state[a].ctypes.data for a in range(6)], status.ctypes.data, nst.ctypes.data,
              vol.ctypes.data, mpos.ctypes.data, mp.ctypes.data, _ptr(trace), trace_steps,
-             _ptr(kicks), kick_steps)
+             _ptr(kicks), kick_steps, _ptr(smarg))
     rc = L.oracle_propagate(C.byref(prob.struct), n, C.byref(I), C.byref(O), int(n_threads))
     if rc != 0:
         raise RuntimeError(f"oracle_propagate failed with code {rc}")
-    return Result(out_state, status, nst, vol, mpos, mp, trace, kicks)
+    return Result(out_state, status, nst, vol, mpos, mp, trace, kicks, smarg)
 
 
 # --------------------------------------------------------------------------

@@ -320,6 +320,7 @@ typedef struct {
     int32_t trace_steps;
     float *kicks;                   /* [n][kick_steps][3] (f, tau, phi/2pi) or NULL */
     int32_t kick_steps;
+    double *step_margin;            /* [n][trace_steps + 1][2] (pos, p) per step, or NULL */
 } orc_out;
 
 static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
@@ -342,14 +343,21 @@ static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
         (in->q[j] != 1 && in->q[j] != -1))
         status = ST_INVALID;
 
+    double *sm = NULL;              /* this step's (pos, p) margins */
     while (status == 0) {
         double pm = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        double kpos = INFINITY, kp = INFINITY;
+        sm = (out->step_margin && k <= out->trace_steps)
+                 ? out->step_margin + ((int64_t)j * (out->trace_steps + 1) + k) * 2 : NULL;
         /* margins of the break test */
         double d;
-        d = fabs(pm - P->p_min) / pm;               if (d < mp) mp = d;
-        d = fabs(r[2] - P->world[2]);               if (d < mpos) mpos = d;
-        d = fabs(fabs(r[0]) - P->world[0]);         if (d < mpos) mpos = d;
-        d = fabs(fabs(r[1]) - P->world[1]);         if (d < mpos) mpos = d;
+        d = fabs(pm - P->p_min) / pm;               if (d < kp) kp = d;
+        d = fabs(r[2] - P->world[2]);               if (d < kpos) kpos = d;
+        d = fabs(fabs(r[0]) - P->world[0]);         if (d < kpos) kpos = d;
+        d = fabs(fabs(r[1]) - P->world[1]);         if (d < kpos) kpos = d;
+        if (kpos < mpos) mpos = kpos;
+        if (kp < mp) mp = kp;
+        if (sm) { sm[0] = kpos; sm[1] = kp; }
         if (pm < P->p_min) { status = ST_PMIN; break; }
         if (r[2] >= P->world[2]) { status = ST_ZMAX; break; }
         if (fabs(r[0]) >= P->world[0]) { status = ST_XMAX; break; }
@@ -357,15 +365,19 @@ static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
         if (k >= P->max_steps) { status = ST_STEPS; break; }
 
         int32_t vol = oracle_lookup(P, r);
-        d = orc_geom_margin(P, r);                  if (d < mpos) mpos = d;
+        d = orc_geom_margin(P, r);
+        if (d < mpos) mpos = d;
+        if (sm && d < sm[0]) sm[0] = d;
         int32_t mat = vol >= 0 ? P->material[vol] : -1;
         int32_t ibin = -1;
         int64_t cell = -1;
         if (mat >= 0) {
             ibin = oracle_pbin(P, pm);
             /* margin to the edges bracketing the chosen bin */
-            d = fabs(pm - P->p_edges[ibin]) / pm;     if (d < mp) mp = d;
-            d = fabs(pm - P->p_edges[ibin + 1]) / pm; if (d < mp) mp = d;
+            d = fabs(pm - P->p_edges[ibin]) / pm;
+            if (fabs(pm - P->p_edges[ibin + 1]) / pm < d) d = fabs(pm - P->p_edges[ibin + 1]) / pm;
+            if (d < mp) mp = d;
+            if (sm && d < sm[1]) sm[1] = d;
             uint32_t ctr[4] = {(uint32_t)mu, (uint32_t)((uint64_t)mu >> 32), (uint32_t)k, 0u};
             uint32_t w[4];
             oracle_philox(ctr, key, w);
@@ -403,8 +415,9 @@ static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
     out->n_steps[j] = k;
     out->volume[j] = status == ST_INVALID ? -1 : oracle_lookup(P, r);
     if (status != ST_INVALID) {
-        double d = orc_geom_margin(P, r);
+        double d = orc_geom_margin(P, r);     /* the final-volume lookup */
         if (d < mpos) mpos = d;
+        if (sm && d < sm[0]) sm[0] = d;
     }
     if (out->margin_pos) out->margin_pos[j] = mpos;
     if (out->margin_p) out->margin_p[j] = mp;

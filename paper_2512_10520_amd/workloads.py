@@ -421,6 +421,6 @@ def make_workload(name: str, n_muons: Optional[int] = None, n_fill: int = 1_000_
                                   n_variants=v, scales=scales))
     # diff: unit scales, the block muons, transport to z = 5 m (<= 251 steps).
     return Workload(name, hist, geom, None, _power_law_muons(2, n, _Z0_BLOCK),
-                    RunParams(step=step, max_steps=256, p_min=0.18, seed=0,
+                    RunParams(step=step, max_steps=400, p_min=0.18, seed=0,
                               n_variants=1, scales=np.ones((1, geom.n_mag), np.float32)),
                     extra={"z_det": 30.0, "r_ap": 1.0, "r_scale": 0.01})

@@ -2,20 +2,23 @@
 binding, run the oracle on the same muons, and compare.
 
 Parity bar (GPU FP32 stages with FP64 state vs the FP64 oracle):
-  - muons whose oracle decision margin is below DELTA_POS (positions, m) or
-    DELTA_P (relative momentum) are "tie class": a decision there can go
-    either way under rounding and they are left out of the exact comparison
-    (and counted);
-  - for all other muons: status, step count, final volume and the per-step
-    (volume, momentum bin, cell) trace agree exactly; final positions within
-    1e-4 * max(|r|, 1 m) and momenta within 1e-4 * |p|.
+  - status, step count, final volume and the per-step (volume, momentum bin,
+    cell) trace agree exactly, final positions within 1e-4 * max(|r|, 1 m)
+    and momenta within 1e-4 * |p|;
+  - except for "tie" muons: a muon may part ways with the oracle only at a
+    decision whose oracle margin is below DELTA_POS (distance to a face or
+    threshold, m) or DELTA_P (relative distance of |p| to a bin edge or to
+    p_min).  Such a decision can go either way under rounding; these muons
+    are counted and their number is bounded per test.
+DELTA_POS and DELTA_P are at least 10x the largest GPU-oracle deviation of
+the agreeing muons observed in these tests.
 """
 import numpy as np
 
 import oracle
 
-DELTA_POS = 2e-5     # m
-DELTA_P = 2e-6       # relative
+DELTA_POS = 1e-5     # m
+DELTA_P = 1e-6       # relative
 REL_TOL = 1e-4
 
 
@@ -49,6 +52,8 @@ def gpu_run(wl, n=None, mode="plain", trace_steps=0, n_trace=0, scales=None, blo
 
 
 def oracle_run(wl, idx, variant=None, trace_steps=0, scales=None):
+    """Oracle on muons idx (Philox indices), with per-step traces and margins
+    when trace_steps > 0."""
     sc = scales
     if sc is None and wl.run.scales is not None:
         sc = np.asarray(wl.run.scales, np.float64)
@@ -56,46 +61,73 @@ def oracle_run(wl, idx, variant=None, trace_steps=0, scales=None):
                             trace_steps=trace_steps, scales=sc)
 
 
-def compare(gpu, ora, sel=None, trace_rows=None, max_tie_frac=0.01, label=""):
-    """Compare GPU lanes ``sel`` (default all) with the oracle result rows.
+def _differs(gpu, ora, sel, i):
+    """Does lane sel[i] differ from oracle row i beyond the parity bar?"""
+    g = sel[i]
+    if (gpu["status"][g] != ora.status[i] or gpu["n_steps"][g] != ora.n_steps[i] or
+            gpu["volume"][g] != ora.volume[i]):
+        return True
+    if ora.status[i] == oracle.ST_INVALID:
+        return False
+    r_o, p_o = ora.state[:3, i], ora.state[3:, i]
+    r_g, p_g = gpu["state"][:3, g], gpu["state"][3:, g]
+    if np.linalg.norm(r_g - r_o) > REL_TOL * max(np.linalg.norm(r_o), 1.0):
+        return True
+    return np.linalg.norm(p_g - p_o) > REL_TOL * np.linalg.norm(p_o)
 
-    ``trace_rows``: number of leading compared muons whose traces both sides
-    recorded.  Returns a dict of statistics."""
-    if sel is None:
-        sel = np.arange(len(ora.status))
+
+def compare(gpu, ora, sel=None, trace_rows=0, max_tie_frac=0.01, label=""):
+    """Compare GPU lanes ``sel`` (default 0..n-1) with the oracle rows.
+
+    A muon may differ only through a boundary tie.  For muons with a trace on
+    both sides (the first ``trace_rows`` rows, oracle run with per-step
+    margins) the first step where the (volume, bin, cell) traces, the step
+    count, the status or the final volume part ways must be a step whose
+    oracle decision margin is below DELTA_POS / DELTA_P.  For the other muons
+    the minimum margin over the whole trajectory must be below them.
+    Everything else must agree: discrete outputs exactly, states within
+    REL_TOL.  Returns statistics (including the largest position / momentum
+    deviations of the agreeing muons, used to calibrate the deltas)."""
+    n = len(ora.status)
+    sel = np.arange(n) if sel is None else np.asarray(sel)
+    agree = np.ones(n, bool)
+    tie = np.zeros(n, bool)
+    for i in range(n):
+        g = sel[i]
+        diverge_k = None
+        if i < trace_rows:
+            T = gpu["trace"].shape[1]
+            m = int(min(gpu["n_steps"][g], ora.n_steps[i], T))
+            d = np.flatnonzero((gpu["trace"][g, :m] != ora.trace[i, :m]).any(axis=1))
+            if d.size:
+                diverge_k = int(d[0])
+            elif _differs(gpu, ora, sel, i):
+                diverge_k = m
+        elif _differs(gpu, ora, sel, i):
+            diverge_k = -1
+        if diverge_k is None:
+            continue
+        agree[i] = False
+        if diverge_k >= 0 and ora.step_margin is not None and diverge_k < ora.step_margin.shape[1] \
+                and not (diverge_k == gpu["trace"].shape[1] and ora.n_steps[i] > diverge_k):
+            mpos, mp = ora.step_margin[i, diverge_k]
+        else:
+            mpos, mp = ora.margin_pos[i], ora.margin_p[i]
+        if mpos < DELTA_POS or mp < DELTA_P:
+            tie[i] = True
+        else:
+            raise AssertionError(
+                f"{label}: lane {g} differs from the oracle with no boundary tie "
+                f"(first divergence at step {diverge_k}, margins pos {mpos:.3g} m, p {mp:.3g}): "
+                f"gpu status/steps/vol {gpu['status'][g]}/{gpu['n_steps'][g]}/{gpu['volume'][g]}, "
+                f"oracle {ora.status[i]}/{ora.n_steps[i]}/{ora.volume[i]}")
+    valid = agree & (ora.status != oracle.ST_INVALID)
     st_g = gpu["state"][:, sel]
-    tie = (ora.margin_pos < DELTA_POS) | (ora.margin_p < DELTA_P)
-    ok = ~tie
-    n = len(sel)
-    stats = {"n": n, "tie": int(tie.sum())}
-    assert tie.mean() <= max_tie_frac, f"{label}: {tie.sum()} of {n} muons are tie class"
-    for key, g_arr, o_arr in (("status", gpu["status"][sel], ora.status),
-                              ("n_steps", gpu["n_steps"][sel], ora.n_steps),
-                              ("volume", gpu["volume"][sel], ora.volume)):
-        bad = np.flatnonzero(ok & (g_arr != o_arr))
-        assert bad.size == 0, (f"{label}: {key} differs for {bad.size} non-tie muons, e.g. lane "
-                               f"{sel[bad[0]]}: gpu {g_arr[bad[0]]} oracle {o_arr[bad[0]]}")
-    valid = ok & (ora.status != oracle.ST_INVALID)
-    r_o, r_g = ora.state[:3], st_g[:3]
-    p_o, p_g = ora.state[3:], st_g[3:]
-    dr = np.linalg.norm(r_g - r_o, axis=0)
-    dp = np.linalg.norm(p_g - p_o, axis=0)
-    rs = np.maximum(np.linalg.norm(r_o, axis=0), 1.0)
-    ps = np.linalg.norm(p_o, axis=0)
-    rel_r = np.where(valid, dr / rs, 0.0)
-    rel_p = np.where(valid, dp / np.where(ps > 0, ps, 1.0), 0.0)
-    stats["max_rel_r"] = float(rel_r.max()) if n else 0.0
-    stats["max_rel_p"] = float(rel_p.max()) if n else 0.0
-    stats["max_abs_r"] = float(np.where(valid, dr, 0).max()) if n else 0.0
-    assert stats["max_rel_r"] <= REL_TOL, f"{label}: position error {stats['max_rel_r']:.3g}"
-    assert stats["max_rel_p"] <= REL_TOL, f"{label}: momentum error {stats['max_rel_p']:.3g}"
-    if trace_rows:
-        tg = gpu["trace"][:trace_rows]
-        to = ora.trace[:trace_rows]
-        for j in range(trace_rows):
-            if not ok[j]:
-                continue
-            k = int(ora.n_steps[j])
-            kk = min(k, tg.shape[1])
-            assert np.array_equal(tg[j, :kk], to[j, :kk]), f"{label}: trace differs, muon {j}"
+    dr = np.linalg.norm(st_g[:3] - ora.state[:3], axis=0)
+    dp = np.linalg.norm(st_g[3:] - ora.state[3:], axis=0)
+    ps = np.linalg.norm(ora.state[3:], axis=0)
+    stats = {"n": n, "tie": int(tie.sum()),
+             "max_abs_dr": float(np.where(valid, dr, 0).max()) if n else 0.0,
+             "max_rel_dp": float(np.where(valid, dp / np.where(ps > 0, ps, 1), 0).max()) if n else 0.0}
+    assert tie.mean() <= max_tie_frac if n else True, f"{label}: {tie.sum()} of {n} muons diverged"
     return stats

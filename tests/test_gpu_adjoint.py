@@ -1,0 +1,126 @@
+"""GPU adjoint (pathwise gradients) against closed forms and against central
+finite differences of the FP64 oracle on common random numbers.
+
+Tolerance: a central difference with step h has truncation error O(h^2);
+with the 1 cm sigmoid of the detector loss and h = 1e-3 that is up to about
+1-2 % per muon.  The reference is therefore the Richardson combination
+(4 D(h/2) - D(h)) / 3, whose error is O(h^4); the adjoint must match it to
+2e-3 relative (FP32 stage arithmetic on the GPU side) and must also lie
+within the spread |D(h) - Richardson| of the plain central difference.
+Muons whose discrete decisions differ between any +h/-h pair are flagged by
+the oracle and left out on both sides.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_10520_amd import workloads as W
+from tests import _custom as CU
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    return t
+
+
+def _gpu_grads(torch, wl, idx, mask=None, z_det=30.0, r_ap=1.0, r_scale=0.01):
+    from paper_2512_10520_amd import api
+    api.load_workload(wl)
+    mu = wl.muons.take(np.asarray(idx))
+    dm = api.DeviceMuons.from_host(mu)
+    spec = api.RunSpec.from_workload(wl)
+    sc0 = wl.run.scales if wl.run.scales is not None else np.ones((1, wl.geom.n_mag))
+    sc = torch.tensor(np.asarray(sc0, np.float32), device="cuda")
+    use_scales = wl.geom.n_mag > 0
+    x0 = dm.state.clone().requires_grad_(True)
+    s_in = sc.clone().requires_grad_(True) if use_scales else None
+    st, status, nst = api.transport(x0, s_in, dm.q, spec)
+    x, y, z, px, py, pz = st
+    dz = z_det - z
+    r = torch.sqrt((x + dz * px / pz) ** 2 + (y + dz * py / pz) ** 2)
+    term = torch.sigmoid((r_ap - r) / r_scale)
+    keep = status == 2
+    if mask is not None:
+        keep = keep & torch.as_tensor(mask, device="cuda")
+    loss = torch.where(keep, term, torch.zeros_like(term)).sum()
+    loss.backward()
+    g_x0 = x0.grad.cpu().numpy()
+    g_s = s_in.grad.cpu().numpy() if use_scales else None
+    return g_x0, g_s, status.cpu().numpy(), nst.cpu().numpy()
+
+
+def _richardson(f, h):
+    d1, fl1 = f(h)
+    d2, fl2 = f(h / 2)
+    return (4 * d2 - d1) / 3, d1, fl1 | fl2
+
+
+def test_adjoint_straight_line_closed_form(torch):
+    rng = np.random.default_rng(12)
+    n = 300
+    x0, y0 = rng.uniform(0.5, 1.0, n), rng.uniform(-0.4, 0.4, n)
+    px, py, pz = rng.normal(0, 0.05, n), rng.normal(0, 0.05, n), rng.uniform(10, 100, n)
+    mu = CU.muons(x0, y0, -0.0075, px, py, pz, np.where(np.arange(n) % 2, 1, -1))
+    geom = CU.geometry(np.zeros((0, 6)), np.zeros(0), world=(50.0, 50.0, 5.0))
+    wl = CU.workload(CU.flat_histograms(), geom, mu, max_steps=400, p_min=0.1)
+    g, _, status, _ = _gpu_grads(torch, wl, np.arange(n))
+    assert np.all(status == 2)
+    # closed form: x_d = x0 + (30 - z0) px/pz, y_d likewise; autograd on CPU in FP64
+    st = torch.tensor(mu.stacked(), dtype=torch.float64, requires_grad=True)
+    x, y, z, a, b, c = st
+    xd, yd = x + (30 - z) * a / c, y + (30 - z) * b / c
+    torch.sigmoid((1.0 - torch.sqrt(xd * xd + yd * yd)) / 0.01).sum().backward()
+    ref = st.grad.numpy()
+    scale = np.abs(ref).max()
+    assert np.allclose(g, ref, rtol=1e-5, atol=1e-6 * scale)
+
+
+def test_adjoint_scales_vs_oracle_fd(torch):
+    wl = W.make_workload("diff", n_muons=600, n_fill=200_000)
+    idx = np.arange(600)
+    ref, d1, flag = _richardson(lambda h: oracle.fd_scales(wl, idx, h=h), 1e-3)
+    _, gs, status, _ = _gpu_grads(torch, wl, idx, mask=~flag)
+    gs = gs[0]
+    print("adjoint dL/ds", gs, "\nrichardson", ref, "\nfd(h)", d1, "\nflagged", flag.sum())
+    assert flag.mean() < 0.05
+    assert np.all(np.abs(ref) > 1e-2)
+    assert np.allclose(gs, ref, rtol=2e-3, atol=0)
+    assert np.all(np.abs(gs - ref) <= np.abs(d1 - ref) + 1e-3 * np.abs(ref))
+
+
+def test_adjoint_inputs_vs_oracle_fd(torch):
+    wl = W.make_workload("diff", n_muons=150, n_fill=200_000)
+    idx = np.arange(150)
+    comps = (0, 1, 3, 4, 5)
+    ref, d1, flag = _richardson(lambda h: oracle.fd_inputs(wl, idx, h=h, comps=comps), 1e-3)
+    g, _, status, _ = _gpu_grads(torch, wl, idx, mask=~flag)
+    keep = (~flag) & (status == 2)
+    assert keep.sum() > 80
+    for a in comps:
+        r, gg = ref[a, keep], g[a, keep]
+        scale = np.abs(r).max()
+        bad = np.abs(gg - r) > 2e-3 * np.abs(r) + 1e-4 * scale
+        assert not bad.any(), (a, np.flatnonzero(bad)[:5], gg[bad][:5], r[bad][:5])
+
+
+def test_adjoint_with_field_map_inputs(torch):
+    """Shield geometry (trilinear map, several materials): gradients with
+    respect to the initial state through the map's spatial derivative."""
+    wl = W.make_workload("shield", n_muons=400, n_fill=200_000)
+    idx = np.arange(400)
+    kw = dict(z_det=35.0)
+    comps = (0, 1, 3, 4)
+    ref, d1, flag = _richardson(lambda h: oracle.fd_inputs(wl, idx, h=h, comps=comps, **kw), 1e-3)
+    g, _, status, _ = _gpu_grads(torch, wl, idx, mask=~flag, z_det=35.0)
+    keep = (~flag) & (status == 2)
+    assert keep.sum() > 20
+    for a in comps:
+        r, gg = ref[a, keep], g[a, keep]
+        scale = np.abs(r).max()
+        bad = np.abs(gg - r) > 5e-3 * np.abs(r) + 1e-3 * scale
+        assert not bad.any(), (a, np.flatnonzero(bad)[:5], gg[bad][:5], r[bad][:5])
