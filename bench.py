@@ -53,7 +53,22 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-design", action="store_true")
     ap.add_argument("--cpu-muons", type=int, default=400_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(torch, nbytes=1 << 30, reps=4):
+    """A plain device-to-device copy of known size: FETCH_SIZE / WRITE_SIZE of
+    this kernel per dispatch give the counters' scale (bytes read and written
+    are nbytes each)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def _time_launches(fn, k, torch):
@@ -80,6 +95,10 @@ def main():
         sys.exit(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the transport "
                  "shards by muon index across GPUs, but this build runs and reports N=1.")
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
 
     from paper_2512_10520_amd import api
     from paper_2512_10520_amd import workloads as W

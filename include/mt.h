@@ -65,6 +65,7 @@ extern "C" {
 /* Documented table limits. */
 #define MT_MAX_BOXES      64     /* boxes in the geometry */
 #define MT_MAX_PBINS      1024   /* momentum bins */
+#define MT_MAX_HISTS      4096   /* n_mat * n_pbin histograms */
 #define MT_MAX_CELLS      65536  /* n_loss * n_scat per histogram */
 #define MT_MAX_MAGNETS    16     /* scaled magnets */
 
@@ -79,7 +80,8 @@ extern "C" {
  *            e_P use bin P-1 (no interpolation between bins).
  *   counts   host uint32 [n_mat][n_pbin][n_loss][n_scat] (loss index major);
  *            each histogram's total must lie in [1, 2^32).
- * Limits: n_pbin <= MT_MAX_PBINS, n_loss * n_scat <= MT_MAX_CELLS.
+ * Limits: n_pbin <= MT_MAX_PBINS, n_mat * n_pbin <= MT_MAX_HISTS,
+ * n_loss * n_scat <= MT_MAX_CELLS.
  * Errors: MT_ERR_INVALID_ARG, MT_ERR_EMPTY_HIST, MT_ERR_LIMIT, MT_ERR_OOM,
  *         MT_ERR_HIP.
  */
@@ -154,7 +156,7 @@ typedef struct mt_params {
     /* differentiable form */
     int32_t  ckpt_every;      /* 0 = off, or 16: checkpoint (r, p) every 16 steps */
     double  *ckpt;            /* device [ceil(max_steps/16)][6][lanes] */
-    float   *tape;            /* device [max_steps][4][lanes]: local kick (3) + volume bits */
+    float   *tape;            /* device [max_steps][lanes][4]: local kick (3) + volume bits */
     /* per-step trace for the first n_trace lanes */
     int32_t *trace;           /* device [n_trace][trace_steps][3] = volume, bin, cell; or NULL */
     int64_t  n_trace;

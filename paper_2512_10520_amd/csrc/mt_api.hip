@@ -138,8 +138,7 @@ void relayout() {
     const int P = g.T.hist.n_pbin, nb = g.T.geom.n_box, ns = g.T.geom.n_slab;
     const int nh = g.T.hist.n_mat * P;
     L.off_e2 = take(8 * (P + 1), 16);
-    L.totals_in_lds = nh <= mt::kTotalsLdsMax ? 1 : 0;
-    L.off_tot = take(L.totals_in_lds ? 4 * nh : 0, 16);
+    L.off_tot = take(4 * nh, 16);
     L.off_box4 = take(32 * nb, 16);
     L.off_bf = take(16 * nb, 16);
     L.off_mat = take(4 * nb, 16);
@@ -408,6 +407,8 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
             return fail(MT_ERR_INVALID_ARG, "p_edges must be strictly ascending (index %d)", i);
     }
     const int64_t nh = (int64_t)n_mat * n_pbin;
+    if (nh > MT_MAX_HISTS)
+        return fail(MT_ERR_LIMIT, "n_mat * n_pbin = %lld exceeds %d", (long long)nh, MT_MAX_HISTS);
     // Guide resolution: about one guide entry per cell, at most 2^16.
     int gbits = 1;
     while (gbits < 16 && ((int64_t)1 << gbits) < K) ++gbits;
@@ -518,6 +519,15 @@ int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material, 
         bf[b] = b_box ? make_float4(b_box[3 * b], b_box[3 * b + 1], b_box[3 * b + 2], 0.f)
                       : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    bool disjoint = true;
+    for (int a = 0; a < n_box && disjoint; ++a)
+        for (int b = a + 1; b < n_box && disjoint; ++b) {
+            bool overlap = true;
+            for (int ax = 0; ax < 3; ++ax)
+                overlap = overlap && box[6 * a + 2 * ax] < box[6 * b + 2 * ax + 1] &&
+                          box[6 * b + 2 * ax] < box[6 * a + 2 * ax + 1];
+            if (overlap) disjoint = false;
+        }
     std::sort(zs.begin(), zs.end());
     zs.erase(std::unique(zs.begin(), zs.end()), zs.end());
     std::vector<double> slab_z;
@@ -541,6 +551,7 @@ int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material, 
     G.n_box = n_box;
     G.n_slab = n_slab;
     G.n_mag = n_mag;
+    G.disjoint = disjoint ? 1 : 0;
     G.box4 = reinterpret_cast<const double *>(g.box4.p);
     G.material = reinterpret_cast<const int32_t *>(g.material.p);
     G.bfield = reinterpret_cast<const float4 *>(g.bfield.p);
@@ -621,7 +632,9 @@ int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in
     }
     if ((rc = g.scratch.ensure((size_t)mt::adjoint_scratch_bytes(g.T, c.lanes)))) return rc;
     if ((rc = g.gs_lane.ensure((size_t)std::max(1, n_mag) * c.lanes * sizeof(double)))) return rc;
-    const int block = 256;
+    const int block = std::getenv("MT_ADJOINT_BLOCK") ? std::atoi(std::getenv("MT_ADJOINT_BLOCK")) : 128;
+    if (block < 64 || block > 256 || block % 64)
+        return fail(MT_ERR_INVALID_ARG, "MT_ADJOINT_BLOCK must be 64, 128, 192 or 256");
     MT_HIP(mt::launch_adjoint(g.T, c.R, c.io, g_out, g_in,
                               reinterpret_cast<double *>(g.gs_lane.p), g.scratch.p, block, s));
     if (g_scales && n_mag > 0) {

@@ -11,7 +11,6 @@ namespace mt {
 
 constexpr int kWave = 64;
 constexpr int kCkptEvery = 16;             // RK4 state checkpoint interval
-constexpr int kTotalsLdsMax = 4096;        // histogram totals staged in LDS up to this many
 constexpr double kKappa = 0.299792458;     // GeV / (c T m)
 
 // Histogram tables on the device.  cdf[h][c] is the inclusive cumulative
@@ -34,6 +33,7 @@ struct DevHist {
 // ranges of those boxes need testing, lowest index first.
 struct DevGeom {
     int32_t n_box, n_slab, n_mag;
+    int32_t disjoint;            // no two boxes overlap: a box that holds a point is its box
     const double *box4;          // [n_box][4] xlo, xhi, ylo, yhi
     const int32_t *material;     // [n_box]
     const float4 *bfield;        // [n_box] (bx, by, bz, 0)
@@ -54,7 +54,6 @@ struct DevField {
 struct LdsLayout {
     int32_t off_e2, off_tot, off_box4, off_mat, off_bf, off_mag, off_slabz, off_slabm;
     int32_t bytes;
-    int32_t totals_in_lds;
 };
 
 struct DevRun {
@@ -66,7 +65,7 @@ struct DevRun {
     int64_t lanes;               // n_variants * n
     const float *scales;         // [n_variants][n_mag] or nullptr
     double *ckpt;                // [n_ckpt][6][lanes] or nullptr
-    float *tape;                 // [max_steps][4][lanes] or nullptr
+    float *tape;                 // [max_steps][lanes][4] or nullptr
     int32_t *trace;
     int64_t n_trace;
     int32_t trace_steps;

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "mt_internal.h"
 
@@ -25,21 +26,63 @@ namespace {
 // the 64-bit products of counter words 0 and 2 with the two multipliers,
 // the high halves xored with words 1 and 3 and the round key, the key then
 // advanced by the two Weyl increments.  The key is the same for every lane.
+//
+// The counter is (j mod 2^32, j / 2^32, step, 0) for muon j.  Everything in
+// rounds 1 and 2 that does not depend on the step is the same for all steps
+// of a muon, so it is formed once per muon (philox_prefix) and each step
+// starts from it (philox_step): one product in each of the first two rounds
+// instead of two.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                          uint32_t k0, uint32_t k1) {
+constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+
+struct PhiloxPrefix {
+    uint32_t c1;   // round 1: j_hi ^ key0
+    uint32_t c4;   // round 2: hi(kMulB * n2_1) ^ (key0 + kWeylA)
+    uint32_t c5;   // round 2: lo(kMulB * n2_1)
+    uint32_t c6;   // round 2: n3_1 ^ (key1 + kWeylB)
+};
+
+__device__ __forceinline__ PhiloxPrefix philox_prefix(uint32_t jlo, uint32_t jhi, uint32_t k0,
+                                                      uint32_t k1) {
+    const uint64_t pa1 = (uint64_t)kMulA * jlo;
+    const uint32_t n2_1 = (uint32_t)(pa1 >> 32) ^ k1;   // round 1, word 2 (counter word 3 is 0)
+    const uint32_t n3_1 = (uint32_t)pa1;
+    const uint64_t pb2 = (uint64_t)kMulB * n2_1;
+    PhiloxPrefix P;
+    P.c1 = jhi ^ k0;
+    P.c4 = (uint32_t)(pb2 >> 32) ^ (k0 + kWeylA);
+    P.c5 = (uint32_t)pb2;
+    P.c6 = n3_1 ^ (k1 + kWeylB);
+    return P;
+}
+
+__device__ __forceinline__ uint4 philox_step(const PhiloxPrefix &P, uint32_t step, uint32_t k0,
+                                             uint32_t k1) {
+    // round 1: only the product with the step word varies
+    const uint64_t pb1 = (uint64_t)kMulB * step;
+    const uint32_t n0_1 = (uint32_t)(pb1 >> 32) ^ P.c1;
+    const uint32_t n1_1 = (uint32_t)pb1;
+    // round 2
+    const uint64_t pa2 = (uint64_t)kMulA * n0_1;
+    uint32_t c0 = n1_1 ^ P.c4;
+    uint32_t c1 = P.c5;
+    uint32_t c2 = (uint32_t)(pa2 >> 32) ^ P.c6;
+    uint32_t c3 = (uint32_t)pa2;
+    k0 += 2u * kWeylA;
+    k1 += 2u * kWeylB;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
-        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+    for (int r = 2; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
         const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
         const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
         c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
+        k0 += kWeylA;
+        k1 += kWeylB;
     }
     return make_uint4(c0, c1, c2, c3);
 }
@@ -70,10 +113,8 @@ __device__ __forceinline__ Lds stage_tables(char *smem, const Tables &T) {
     uint64_t *slabm = reinterpret_cast<uint64_t *>(smem + L.off_slabm);
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i <= T.hist.n_pbin; i += nt) e2[i] = T.hist.edges2[i];
-    if (L.totals_in_lds) {
-        const int nh = T.hist.n_mat * T.hist.n_pbin;
-        for (int i = tid; i < nh; i += nt) tot[i] = T.hist.totals[i];
-    }
+    const int nh = T.hist.n_mat * T.hist.n_pbin;
+    for (int i = tid; i < nh; i += nt) tot[i] = T.hist.totals[i];
     for (int i = tid; i < 4 * T.geom.n_box; i += nt) box4[i] = T.geom.box4[i];
     for (int i = tid; i < T.geom.n_box; i += nt) {
         mat[i] = T.geom.material[i];
@@ -87,13 +128,17 @@ __device__ __forceinline__ Lds stage_tables(char *smem, const Tables &T) {
 }
 
 // ---------------------------------------------------------------------------
-// Lane state.
+// Lane state.  Besides the muon, a lane caches what rarely changes from one
+// step to the next: the z-slab, the box, the momentum bin and the scaled
+// field of the box.  Cached values are the
+// same numbers a fresh lookup gives, so caching never changes a result.
 // ---------------------------------------------------------------------------
 struct Lane {
     double x, y, z, px, py, pz;
     float q;
-    int32_t k, status, ibin, slab, var;
-    uint32_t jlo, jhi;
+    float bx, by, bz;     // scaled field of box bvol
+    int32_t k, status, ibin, slab, vol, bvol, var;
+    PhiloxPrefix ph;
     int64_t g;
 };
 
@@ -112,12 +157,14 @@ __device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, c
     const int qi = io.q[j];
     L.q = (float)qi;
     L.var = (int32_t)var;
-    L.jlo = (uint32_t)j;
-    L.jhi = (uint32_t)((uint64_t)j >> 32);
+    L.ph = philox_prefix((uint32_t)j, (uint32_t)((uint64_t)j >> 32), R.key0, R.key1);
     L.g = g;
     L.k = 0;
     L.ibin = -1;
     L.slab = -1;
+    L.vol = -1;
+    L.bvol = -2;
+    L.bx = L.by = L.bz = 0.0f;
     L.status = MT_ST_RUNNING;
     const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
     const bool ok = isfinite(L.x) && isfinite(L.y) && isfinite(L.z) && isfinite(p2) &&
@@ -142,15 +189,32 @@ __device__ __forceinline__ int find_slab(const Lds &S, int n_slab, double z, int
     return s;
 }
 
+__device__ __forceinline__ bool in_box_xy(const Lds &S, int b, double x, double y) {
+    const double *bx = S.box4 + 4 * b;
+    return bx[0] <= x && x < bx[1] && bx[2] <= y && y < bx[3];
+}
+
 __device__ __forceinline__ int find_box(const Lds &S, int s, double x, double y) {
     uint64_t m = S.slabm[s];
     while (m) {
         const int b = __builtin_ctzll(m);
-        const double *bx = S.box4 + 4 * b;
-        if (bx[0] <= x && x < bx[1] && bx[2] <= y && y < bx[3]) return b;
+        if (in_box_xy(S, b, x, y)) return b;
         m &= m - 1;
     }
     return -1;
+}
+
+// Box containing the lane's position (lowest index), using the cached slab
+// and, for geometries without overlapping boxes, the cached box.
+__device__ __forceinline__ int locate(Lane &L, const Tables &T, const Lds &S) {
+    const bool same_slab = L.slab >= 0 && L.z >= S.slabz[L.slab] && L.z < S.slabz[L.slab + 1];
+    if (!same_slab) {
+        L.slab = find_slab(S, T.geom.n_slab, L.z, L.slab);
+    } else if (L.vol >= 0 && T.geom.disjoint && in_box_xy(S, L.vol, L.x, L.y)) {
+        return L.vol;
+    }
+    L.vol = find_box(S, L.slab, L.x, L.y);
+    return L.vol;
 }
 
 // Momentum bin i with e_i^2 <= |p|^2 < e_{i+1}^2, clamped to [0, P-1]; the
@@ -169,19 +233,20 @@ __device__ __forceinline__ int find_bin(const Lds &S, int P, double p2, int i) {
     return i;
 }
 
+__device__ __forceinline__ int bin_of(Lane &L, const Tables &T, const Lds &S, double p2) {
+    L.ibin = find_bin(S, T.hist.n_pbin, p2, L.ibin);
+    return L.ibin;
+}
+
 // Exact inverse CDF: t = floor(w * T / 2^32), cell = smallest c with C[c] > t.
 // The guide entry of the word's top bits brackets c, so most draws need no
 // probe of C at all.
-__device__ __forceinline__ int sample_cell(const DevHist &H, const Lds &S, bool tot_lds, int h,
-                                           uint32_t w0) {
-    const uint32_t T = tot_lds ? S.tot[h] : H.totals[h];
+__device__ __forceinline__ int sample_cell(const DevHist &H, const Lds &S, int h, uint32_t w0) {
+    const uint32_t T = S.tot[h];
     const uint32_t t = __umulhi(w0, T);
-    int lo = 0, hi = H.n_cells - 1;
-    if (H.guide != nullptr) {
-        const uint32_t pk = H.guide[((size_t)h << H.gbits) | (w0 >> (32 - H.gbits))];
-        lo = (int)(pk & 0xFFFFu);
-        hi = (int)(pk >> 16);
-    }
+    const uint32_t pk = H.guide[((size_t)h << H.gbits) | (w0 >> (32 - H.gbits))];
+    int lo = (int)(pk & 0xFFFFu);
+    int hi = (int)(pk >> 16);
     const uint32_t *C = H.cdf + (size_t)h * H.n_cells;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -191,32 +256,35 @@ __device__ __forceinline__ int sample_cell(const DevHist &H, const Lds &S, bool 
 }
 
 // ---------------------------------------------------------------------------
-// Kick: p <- p + R(p_hat) (|p| u), u = (tau cos phi, tau sin phi, -f), with the
-// division-free Rodrigues form R v = c v + a x v + (a.v) a / (1 + c),
-// a = z x p_hat = (-ny, nx, 0), c = nz (equal to Eq. (2) with k = a/|a|).
+// Kick: p <- p + R(p_hat) (|p| u), u = (tau cos phi, tau sin phi, -f).  The
+// rotation maps the local z axis onto p_hat, so the loss part is exactly
+// -f p and is applied in FP64 (it is what accumulates over a trajectory);
+// the transverse part uses the division-free Rodrigues form
+// R v = c v + a x v + (a.v) a / (1 + c), a = z x p_hat = (-ny, nx, 0),
+// c = nz (equal to Eq. (2) with k = a/|a|), in FP32.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void kick(Lane &L, double p2, float ux, float uy, float uz) {
     const float p2f = (float)p2;
     const float rinv = __builtin_amdgcn_rsqf(p2f);
     const float pm = p2f * rinv;
     const float nx = (float)L.px * rinv, ny = (float)L.py * rinv, nz = (float)L.pz * rinv;
-    const float dx = pm * ux, dy = pm * uy, dz = pm * uz;
+    const float dx = pm * ux, dy = pm * uy;
     const float opc = 1.0f + nz;
-    float rx, ry, rz;
+    float tx, ty, tz;
     if (opc > 0.0f) {
-        const float adot = fmaf(nx, dy, -ny * dx);
-        const float coef = adot * __builtin_amdgcn_rcpf(opc);
-        rx = fmaf(nz, dx, fmaf(nx, dz, -coef * ny));
-        ry = fmaf(nz, dy, fmaf(ny, dz, coef * nx));
-        rz = fmaf(nz, dz, -fmaf(nx, dx, ny * dy));
+        const float coef = fmaf(nx, dy, -ny * dx) * __builtin_amdgcn_rcpf(opc);
+        tx = fmaf(nz, dx, -coef * ny);
+        ty = fmaf(nz, dy, coef * nx);
+        tz = -fmaf(nx, dx, ny * dy);
     } else {                           // exactly backwards: rotation by pi about x
-        rx = dx;
-        ry = -dy;
-        rz = -dz;
+        tx = dx;
+        ty = -dy;
+        tz = 0.0f;
     }
-    L.px += (double)rx;
-    L.py += (double)ry;
-    L.pz += (double)rz;
+    const double keep = 1.0 + (double)uz;       // 1 - f, exact
+    L.px = fma(L.px, keep, (double)tx);
+    L.py = fma(L.py, keep, (double)ty);
+    L.pz = fma(L.pz, keep, (double)tz);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,9 +333,8 @@ __device__ __forceinline__ float3 trilerp(const Corner8 &c) {
     return r;
 }
 
-template <bool MAP>
-__device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const DevRun &R, int vol,
-                                           int var, double x, double y, double z) {
+__device__ __forceinline__ float3 box_field(const Tables &T, const Lds &S, const DevRun &R,
+                                            int vol, int var) {
     float3 B = make_float3(0.f, 0.f, 0.f);
     if (vol >= 0) {
         const float4 b = S.bf[vol];
@@ -275,6 +342,11 @@ __device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const 
         const float s = (m >= 0 && R.scales != nullptr) ? R.scales[var * T.geom.n_mag + m] : 1.0f;
         B = make_float3(b.x * s, b.y * s, b.z * s);
     }
+    return B;
+}
+
+template <bool MAP>
+__device__ __forceinline__ float3 add_map(const Tables &T, float3 B, double x, double y, double z) {
     if (MAP) {
         Corner8 c;
         if (map_cell(T.field, x, y, z, c)) {
@@ -285,6 +357,12 @@ __device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const 
         }
     }
     return B;
+}
+
+template <bool MAP>
+__device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const DevRun &R, int vol,
+                                           int var, double x, double y, double z) {
+    return add_map<MAP>(T, box_field(T, S, R, vol, var), x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -355,30 +433,30 @@ __device__ __forceinline__ void rk4(Lane &L, float3 B, const StepConst &c) {
 // One iteration of the transport loop.  Returns false (with L.status set)
 // when a break condition holds at the top of the iteration.
 // ---------------------------------------------------------------------------
-template <bool MAP, bool TAPE>
+template <bool MAP, bool TAPE, bool TRACE>
 __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, const DevRun &R,
                                         const StepConst &sc) {
     const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
-    int st = MT_ST_RUNNING;
-    if (p2 < R.pmin2) st = MT_ST_PMIN;
-    else if (L.z >= T.geom.z_max) st = MT_ST_ZMAX;
-    else if (fabs(L.x) >= T.geom.x_max) st = MT_ST_XMAX;
-    else if (fabs(L.y) >= T.geom.y_max) st = MT_ST_YMAX;
-    else if (L.k >= R.max_steps) st = MT_ST_MAXSTEPS;
+    // Break test in the order p_min, z_max, x_max, y_max, step cap (the first
+    // that holds decides the status).
+    int st = (L.k >= R.max_steps) ? MT_ST_MAXSTEPS : MT_ST_RUNNING;
+    st = (fabs(L.y) >= T.geom.y_max) ? MT_ST_YMAX : st;
+    st = (fabs(L.x) >= T.geom.x_max) ? MT_ST_XMAX : st;
+    st = (L.z >= T.geom.z_max) ? MT_ST_ZMAX : st;
+    st = (p2 < R.pmin2) ? MT_ST_PMIN : st;
     if (st != MT_ST_RUNNING) {
         L.status = st;
         return false;
     }
-    L.slab = find_slab(S, T.geom.n_slab, L.z, L.slab);
-    const int vol = find_box(S, L.slab, L.x, L.y);
+    const int vol = locate(L, T, S);
     const int mat = vol >= 0 ? S.mat[vol] : -1;
     float ux = 0.0f, uy = 0.0f, uz = 0.0f;
     int cell = -1;
     if (mat >= 0) {
-        L.ibin = find_bin(S, T.hist.n_pbin, p2, L.ibin);
-        const uint4 w = philox10(L.jlo, L.jhi, (uint32_t)L.k, 0u, R.key0, R.key1);
-        const int h = mat * T.hist.n_pbin + L.ibin;
-        cell = sample_cell(T.hist, S, T.lds.totals_in_lds != 0, h, w.x);
+        const int ibin = bin_of(L, T, S, p2);
+        const uint4 w = philox_step(L.ph, (uint32_t)L.k, R.key0, R.key1);
+        const int h = mat * T.hist.n_pbin + ibin;
+        cell = sample_cell(T.hist, S, h, w.x);
         const int il = (int)__umulhi((uint32_t)cell, T.hist.nscat_magic);
         const int is = cell - il * T.hist.n_scat;
         const float v1 = (float)(w.y >> 8) * 0x1p-24f;
@@ -395,19 +473,23 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         kick(L, p2, ux, uy, uz);
     }
     if (TAPE) {
-        float *tp = R.tape + (size_t)L.k * 4 * R.lanes + L.g;
-        tp[0] = ux;
-        tp[R.lanes] = uy;
-        tp[2 * R.lanes] = uz;
-        tp[3 * R.lanes] = __int_as_float(vol);
+        reinterpret_cast<float4 *>(R.tape)[(size_t)L.k * R.lanes + L.g] =
+            make_float4(ux, uy, uz, __int_as_float(vol));
     }
-    if (L.g < R.n_trace && L.k < R.trace_steps) {
+    if (TRACE && L.g < R.n_trace && L.k < R.trace_steps) {
         int32_t *tr = R.trace + ((size_t)L.g * R.trace_steps + L.k) * 3;
         tr[0] = vol;
         tr[1] = mat >= 0 ? L.ibin : -1;
         tr[2] = cell;
     }
-    const float3 B = field_at<MAP>(T, S, R, vol, L.var, L.x, L.y, L.z);
+    if (vol != L.bvol) {
+        const float3 b = box_field(T, S, R, vol, L.var);
+        L.bx = b.x;
+        L.by = b.y;
+        L.bz = b.z;
+        L.bvol = vol;
+    }
+    const float3 B = add_map<MAP>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
     rk4(L, B, sc);
     ++L.k;
     return true;
@@ -454,7 +536,7 @@ __device__ __forceinline__ void write_ckpt(const Lane &L, const DevRun &R) {
 // ---------------------------------------------------------------------------
 // Plain form: one lane per (variant, muon) until it stops.
 // ---------------------------------------------------------------------------
-template <bool MAP, bool CKPT>
+template <bool MAP, bool CKPT, bool TRACE>
 __global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
     extern __shared__ __align__(16) char smem[];
     const Lds S = stage_tables(smem, T);
@@ -466,7 +548,7 @@ __global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
     if (L.status == MT_ST_RUNNING) {
         for (;;) {
             if (CKPT && (L.k % kCkptEvery) == 0 && L.k < R.max_steps) write_ckpt(L, R);
-            if (!advance<MAP, CKPT>(L, T, S, R, sc)) break;
+            if (!advance<MAP, CKPT, TRACE>(L, T, S, R, sc)) break;
         }
     }
     store_lane(L, T, S, io);
@@ -480,7 +562,7 @@ __global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
 // plain form because the random stream is keyed by (muon, step), not by lane.
 // A wave exits once the queue is exhausted and all of its lanes are idle.
 // ---------------------------------------------------------------------------
-template <bool MAP>
+template <bool MAP, bool TRACE>
 __global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO io, int compact,
                                                      unsigned long long *queue) {
     extern __shared__ __align__(16) char smem[];
@@ -513,7 +595,7 @@ __global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO i
             continue;
         }
         for (int c = 0; c < compact; ++c) {
-            if (active && !advance<MAP, false>(L, T, S, R, sc)) {
+            if (active && !advance<MAP, false, TRACE>(L, T, S, R, sc)) {
                 store_lane(L, T, S, io);
                 active = false;
             }
@@ -556,21 +638,21 @@ __device__ __forceinline__ float3 kick_f32(float3 p, float3 u) {
     const float rinv = __builtin_amdgcn_rsqf(p2f);
     const float pm = p2f * rinv;
     const float nx = p.x * rinv, ny = p.y * rinv, nz = p.z * rinv;
-    const float dx = pm * u.x, dy = pm * u.y, dz = pm * u.z;
+    const float dx = pm * u.x, dy = pm * u.y;
     const float opc = 1.0f + nz;
-    float rx, ry, rz;
+    float tx, ty, tz;
     if (opc > 0.0f) {
-        const float adot = fmaf(nx, dy, -ny * dx);
-        const float coef = adot * __builtin_amdgcn_rcpf(opc);
-        rx = fmaf(nz, dx, fmaf(nx, dz, -coef * ny));
-        ry = fmaf(nz, dy, fmaf(ny, dz, coef * nx));
-        rz = fmaf(nz, dz, -fmaf(nx, dx, ny * dy));
+        const float coef = fmaf(nx, dy, -ny * dx) * __builtin_amdgcn_rcpf(opc);
+        tx = fmaf(nz, dx, -coef * ny);
+        ty = fmaf(nz, dy, coef * nx);
+        tz = -fmaf(nx, dx, ny * dy);
     } else {
-        rx = dx;
-        ry = -dy;
-        rz = -dz;
+        tx = dx;
+        ty = -dy;
+        tz = 0.0f;
     }
-    return make_float3(p.x + rx, p.y + ry, p.z + rz);
+    const float keep = 1.0f + u.z;
+    return make_float3(fmaf(p.x, keep, tx), fmaf(p.y, keep, ty), fmaf(p.z, keep, tz));
 }
 
 // Gradient of l . g_u(p) with g_u(p) = p_z u + A x u + (A.u) A / (|p| + p_z),
@@ -606,18 +688,121 @@ __device__ __forceinline__ float3 map_grad_t(const DevField &F, const Corner8 &c
     return make_float3(dx * (float)F.inv_d[0], dy * (float)F.inv_d[1], dz * (float)F.inv_d[2]);
 }
 
+// One reverse step: (lr, lp) of the state after step k -> before step k, and
+// the step's contribution to the scale gradient of its magnet.  p0 is the
+// momentum at the start of the step (FP32 is enough for Jacobians), (rx, ry,
+// rz) its position (used only with a field map).
 template <bool MAP>
+__device__ __forceinline__ void reverse_step(const Tables &T, const Lds &S, const DevRun &R,
+                                             const StepConst &sc, float kq, int var, float3 p0,
+                                             double rx, double ry, double rz, int vol, float3 u,
+                                             double lr[3], double lp[3], double *sgs, int bd) {
+    const int mat = vol >= 0 ? S.mat[vol] : -1;
+    const float3 a0 = mat >= 0 ? kick_f32(p0, u) : p0;
+    const float3 B = field_at<MAP>(T, S, R, vol, var, rx, ry, rz);
+    const float3 Lr = make_float3((float)lr[0], (float)lr[1], (float)lr[2]);
+    const float3 Lp = make_float3((float)lp[0], (float)lp[1], (float)lp[2]);
+    // RK4 stages of the step (the straight-line shortcut of the forward pass
+    // equals them at B = 0, so one form serves both).
+    const float3 cb = scale3(kq, B);
+    const float r0 = __builtin_amdgcn_rsqf(norm2(a0));
+    const float3 n0 = scale3(r0, a0);
+    const float3 k1v = cross3(n0, cb);
+    const float3 a1 = axpy(sc.h2, k1v, a0);
+    const float r1 = __builtin_amdgcn_rsqf(norm2(a1));
+    const float3 n1 = scale3(r1, a1);
+    const float3 k2v = cross3(n1, cb);
+    const float3 a2 = axpy(sc.h2, k2v, a0);
+    const float r2 = __builtin_amdgcn_rsqf(norm2(a2));
+    const float3 n2 = scale3(r2, a2);
+    const float3 k3v = cross3(n2, cb);
+    const float3 a3 = axpy(sc.h, k3v, a0);
+    const float r3 = __builtin_amdgcn_rsqf(norm2(a3));
+    const float3 n3 = scale3(r3, a3);
+    // Reverse through k4 = c n3 x B, a3 = a0 + h k3, ..., k1 = c n0 x B.
+    float3 lk3 = scale3(sc.h3, Lp);
+    float3 lk2 = scale3(sc.h3, Lp);
+    float3 lk1 = scale3(sc.h6, Lp);
+    const float3 lk4 = scale3(sc.h6, Lp);
+    float3 lBc = cross3(lk4, n3);
+    float3 la = unit_jt(n3, r3, axpy(sc.h6, Lr, cross3(cb, lk4)));
+    float3 corr = la;
+    lk3 = axpy(sc.h, la, lk3);
+    lBc = add3(lBc, cross3(lk3, n2));
+    la = unit_jt(n2, r2, axpy(sc.h3, Lr, cross3(cb, lk3)));
+    corr = add3(corr, la);
+    lk2 = axpy(sc.h2, la, lk2);
+    lBc = add3(lBc, cross3(lk2, n1));
+    la = unit_jt(n1, r1, axpy(sc.h3, Lr, cross3(cb, lk2)));
+    corr = add3(corr, la);
+    lk1 = axpy(sc.h2, la, lk1);
+    lBc = add3(lBc, cross3(lk1, n0));
+    la = unit_jt(n0, r0, axpy(sc.h6, Lr, cross3(cb, lk1)));
+    corr = add3(corr, la);
+    const float3 lB = scale3(kq, lBc);
+    // lambda of a0 (post-kick momentum), then through the kick
+    double la0[3] = {lp[0] + (double)corr.x, lp[1] + (double)corr.y, lp[2] + (double)corr.z};
+    if (mat >= 0) {
+        const float3 l = make_float3((float)la0[0], (float)la0[1], (float)la0[2]);
+        const float3 kc = kick_adjoint_corr(p0, u, l);
+        la0[0] += (double)kc.x;
+        la0[1] += (double)kc.y;
+        la0[2] += (double)kc.z;
+    }
+    lp[0] = la0[0];
+    lp[1] = la0[1];
+    lp[2] = la0[2];
+    if (vol >= 0) {
+        const int m = S.mag[vol];
+        if (m >= 0) {
+            const float4 b = S.bf[vol];
+            sgs[m * bd] += (double)fmaf(lB.x, b.x, fmaf(lB.y, b.y, lB.z * b.z));
+        }
+    }
+    if (MAP) {
+        Corner8 cc;
+        if (map_cell(T.field, rx, ry, rz, cc)) {
+            const float3 gr = map_grad_t(T.field, cc, lB);
+            lr[0] += (double)gr.x;
+            lr[1] += (double)gr.y;
+            lr[2] += (double)gr.z;
+        }
+    }
+}
+
+// Re-run one step of a segment with its recorded kick and volume (the
+// arithmetic of advance(), so the same bits).
+template <bool MAP>
+__device__ __forceinline__ void replay_step(Lane &L, const Tables &T, const Lds &S,
+                                            const DevRun &R, const StepConst &sc, int var,
+                                            float4 rec) {
+    const int vol = __float_as_int(rec.w);
+    const int mat = vol >= 0 ? S.mat[vol] : -1;
+    if (mat >= 0) {
+        const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
+        kick(L, p2, rec.x, rec.y, rec.z);
+    }
+    const float3 B = field_at<MAP>(T, S, R, vol, var, L.x, L.y, L.z);
+    rk4(L, B, sc);
+}
+
+// The segment's start momenta are kept either in LDS (LDSH) or in a per-lane
+// scratch area in device memory; with a field map the start positions are
+// needed too and always go to the scratch area.
+template <bool MAP, bool LDSH>
 __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
                                                  double *g_in, double *gs_lane, char *scratch) {
     extern __shared__ __align__(16) char smem[];
     const Lds S = stage_tables(smem, T);
     const StepConst sc = step_const(R);
-    double *sgs = reinterpret_cast<double *>(smem + ((T.lds.bytes + 15) & ~15)) + threadIdx.x;
     const int bd = blockDim.x;
+    const int n_mag = T.geom.n_mag;
+    double *sgs = reinterpret_cast<double *>(smem + ((T.lds.bytes + 15) & ~15)) + threadIdx.x;
+    float *hist = reinterpret_cast<float *>(smem + ((T.lds.bytes + 15) & ~15) +
+                                            (size_t)n_mag * bd * sizeof(double)) + threadIdx.x;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= R.lanes) return;
     const int64_t lanes = R.lanes;
-    const int n_mag = T.geom.n_mag;
     for (int m = 0; m < n_mag; ++m) sgs[m * bd] = 0.0;
     double lr[3], lp[3];
     for (int a = 0; a < 3; ++a) {
@@ -630,8 +815,6 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
     if (R.lanes != R.n) var = (int)(g / R.n);
     const float q = (float)io.q[g - (int64_t)var * R.n];
     const float kq = (float)kKappa * q;
-    float *hp = reinterpret_cast<float *>(scratch);
-    double *hr = reinterpret_cast<double *>(scratch + (size_t)kCkptEvery * 3 * sizeof(float) * lanes);
 
     if (status != MT_ST_INVALID && ns > 0) {
         for (int seg = (ns - 1) / kCkptEvery; seg >= 0; --seg) {
@@ -646,114 +829,60 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
             L.py = c[4 * lanes];
             L.pz = c[5 * lanes];
             L.q = q;
-            // Re-forward the segment from its checkpoint with the recorded
-            // kicks and volumes; the arithmetic is that of advance().
-            for (int k = k0; k < k1; ++k) {
-                float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
-                h[0] = (float)L.px;
-                h[lanes] = (float)L.py;
-                h[2 * lanes] = (float)L.pz;
-                if (MAP) {
-                    double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
-                    hh[0] = L.x;
-                    hh[lanes] = L.y;
-                    hh[2 * lanes] = L.z;
+            // kick records of the segment: one float4 per (step, lane)
+            const float4 *rec = reinterpret_cast<const float4 *>(R.tape) + (size_t)k0 * lanes + g;
+            if (LDSH) {
+                // history[i][c][tid] in LDS, after the staged tables and the
+                // per-lane scale-gradient accumulators
+                float4 next = rec[0];
+                for (int k = k0; k < k1; ++k) {
+                    const float4 cur = next;
+                    if (k + 1 < k1) next = rec[(size_t)(k + 1 - k0) * lanes];
+                    float *h = hist + (size_t)(k - k0) * 3 * bd;
+                    h[0] = (float)L.px;
+                    h[bd] = (float)L.py;
+                    h[2 * bd] = (float)L.pz;
+                    replay_step<MAP>(L, T, S, R, sc, var, cur);
                 }
-                const float *tp = R.tape + (size_t)k * 4 * lanes + g;
-                const int vol = __float_as_int(tp[3 * lanes]);
-                const int mat = vol >= 0 ? S.mat[vol] : -1;
-                if (mat >= 0) {
-                    const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
-                    kick(L, p2, tp[0], tp[lanes], tp[2 * lanes]);
+                next = rec[(size_t)(k1 - 1 - k0) * lanes];
+                for (int k = k1 - 1; k >= k0; --k) {
+                    const float4 cur = next;
+                    if (k > k0) next = rec[(size_t)(k - 1 - k0) * lanes];
+                    const float *h = hist + (size_t)(k - k0) * 3 * bd;
+                    reverse_step<MAP>(T, S, R, sc, kq, var, make_float3(h[0], h[bd], h[2 * bd]),
+                                      0.0, 0.0, 0.0, __float_as_int(cur.w),
+                                      make_float3(cur.x, cur.y, cur.z), lr, lp, sgs, bd);
                 }
-                const float3 B = field_at<MAP>(T, S, R, vol, var, L.x, L.y, L.z);
-                rk4(L, B, sc);
-            }
-            // Reverse sweep.
-            for (int k = k1 - 1; k >= k0; --k) {
-                const float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
-                const float3 p0 = make_float3(h[0], h[lanes], h[2 * lanes]);
-                const float *tp = R.tape + (size_t)k * 4 * lanes + g;
-                const int vol = __float_as_int(tp[3 * lanes]);
-                const int mat = vol >= 0 ? S.mat[vol] : -1;
-                const float3 u = make_float3(tp[0], tp[lanes], tp[2 * lanes]);
-                const float3 a0 = mat >= 0 ? kick_f32(p0, u) : p0;
-                double rx = 0.0, ry = 0.0, rz = 0.0;
-                if (MAP) {
-                    const double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
-                    rx = hh[0];
-                    ry = hh[lanes];
-                    rz = hh[2 * lanes];
-                }
-                const float3 B = field_at<MAP>(T, S, R, vol, var, rx, ry, rz);
-                const float3 Lr = make_float3((float)lr[0], (float)lr[1], (float)lr[2]);
-                const float3 Lp = make_float3((float)lp[0], (float)lp[1], (float)lp[2]);
-                // RK4 stages of the step (the straight-line shortcut of the
-                // forward pass equals them at B = 0, so one form serves both).
-                const float3 cb = scale3(kq, B);
-                const float r0 = __builtin_amdgcn_rsqf(norm2(a0));
-                const float3 n0 = scale3(r0, a0);
-                const float3 k1v = cross3(n0, cb);
-                const float3 a1 = axpy(sc.h2, k1v, a0);
-                const float r1 = __builtin_amdgcn_rsqf(norm2(a1));
-                const float3 n1 = scale3(r1, a1);
-                const float3 k2v = cross3(n1, cb);
-                const float3 a2 = axpy(sc.h2, k2v, a0);
-                const float r2 = __builtin_amdgcn_rsqf(norm2(a2));
-                const float3 n2 = scale3(r2, a2);
-                const float3 k3v = cross3(n2, cb);
-                const float3 a3 = axpy(sc.h, k3v, a0);
-                const float r3 = __builtin_amdgcn_rsqf(norm2(a3));
-                const float3 n3 = scale3(r3, a3);
-                // Reverse through k4 = c n3 x B, a3 = a0 + h k3, ..., k1 = c n0 x B.
-                float3 lk3 = scale3(sc.h3, Lp);
-                float3 lk2 = scale3(sc.h3, Lp);
-                float3 lk1 = scale3(sc.h6, Lp);
-                const float3 lk4 = scale3(sc.h6, Lp);
-                float3 lBc = cross3(lk4, n3);
-                float3 la = unit_jt(n3, r3, axpy(sc.h6, Lr, cross3(cb, lk4)));
-                float3 corr = la;
-                lk3 = axpy(sc.h, la, lk3);
-                lBc = add3(lBc, cross3(lk3, n2));
-                la = unit_jt(n2, r2, axpy(sc.h3, Lr, cross3(cb, lk3)));
-                corr = add3(corr, la);
-                lk2 = axpy(sc.h2, la, lk2);
-                lBc = add3(lBc, cross3(lk2, n1));
-                la = unit_jt(n1, r1, axpy(sc.h3, Lr, cross3(cb, lk2)));
-                corr = add3(corr, la);
-                lk1 = axpy(sc.h2, la, lk1);
-                lBc = add3(lBc, cross3(lk1, n0));
-                la = unit_jt(n0, r0, axpy(sc.h6, Lr, cross3(cb, lk1)));
-                corr = add3(corr, la);
-                const float3 lB = scale3(kq, lBc);
-                // lambda of a0 (post-kick momentum)
-                double la0[3] = {lp[0] + (double)corr.x, lp[1] + (double)corr.y,
-                                 lp[2] + (double)corr.z};
-                if (mat >= 0) {
-                    const float3 l = make_float3((float)la0[0], (float)la0[1], (float)la0[2]);
-                    const float3 kc = kick_adjoint_corr(p0, u, l);
-                    la0[0] += (double)kc.x;
-                    la0[1] += (double)kc.y;
-                    la0[2] += (double)kc.z;
-                }
-                lp[0] = la0[0];
-                lp[1] = la0[1];
-                lp[2] = la0[2];
-                if (vol >= 0) {
-                    const int m = S.mag[vol];
-                    if (m >= 0) {
-                        const float4 b = S.bf[vol];
-                        sgs[m * bd] += (double)fmaf(lB.x, b.x, fmaf(lB.y, b.y, lB.z * b.z));
+            } else {
+                float *hp = reinterpret_cast<float *>(scratch);
+                double *hr = reinterpret_cast<double *>(
+                    scratch + (size_t)kCkptEvery * 3 * sizeof(float) * lanes);
+                for (int k = k0; k < k1; ++k) {
+                    float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
+                    h[0] = (float)L.px;
+                    h[lanes] = (float)L.py;
+                    h[2 * lanes] = (float)L.pz;
+                    if (MAP) {
+                        double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
+                        hh[0] = L.x;
+                        hh[lanes] = L.y;
+                        hh[2 * lanes] = L.z;
                     }
+                    replay_step<MAP>(L, T, S, R, sc, var, rec[(size_t)(k - k0) * lanes]);
                 }
-                if (MAP) {
-                    Corner8 cc;
-                    if (map_cell(T.field, rx, ry, rz, cc)) {
-                        const float3 gr = map_grad_t(T.field, cc, lB);
-                        lr[0] += (double)gr.x;
-                        lr[1] += (double)gr.y;
-                        lr[2] += (double)gr.z;
+                for (int k = k1 - 1; k >= k0; --k) {
+                    const float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
+                    double rx = 0.0, ry = 0.0, rz = 0.0;
+                    if (MAP) {
+                        const double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
+                        rx = hh[0];
+                        ry = hh[lanes];
+                        rz = hh[2 * lanes];
                     }
+                    const float4 cur = rec[(size_t)(k - k0) * lanes];
+                    reverse_step<MAP>(T, S, R, sc, kq, var, make_float3(h[0], h[lanes], h[2 * lanes]),
+                                      rx, ry, rz, __float_as_int(cur.w),
+                                      make_float3(cur.x, cur.y, cur.z), lr, lp, sgs, bd);
                 }
             }
         }
@@ -857,24 +986,36 @@ __global__ void k_pass2(const double *partial, int nb, int n_cols, int n_variant
 hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,
                         hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
-    const int64_t grid = (R.lanes + block - 1) / block;
+    const unsigned grid = (unsigned)((R.lanes + block - 1) / block);
     const bool map = T.field.map != nullptr;
     const bool ck = R.ckpt != nullptr;
+    const bool tr = R.n_trace > 0;
     const size_t shm = (size_t)T.lds.bytes;
-    if (map && ck) hipLaunchKernelGGL((k_plain<true, true>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
-    else if (map) hipLaunchKernelGGL((k_plain<true, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
-    else if (ck) hipLaunchKernelGGL((k_plain<false, true>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
-    else hipLaunchKernelGGL((k_plain<false, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io);
+#define MT_PLAIN(A, B, C) \
+    hipLaunchKernelGGL((k_plain<A, B, C>), dim3(grid), dim3(block), shm, s, T, R, io)
+    if (map) {
+        if (ck) { if (tr) MT_PLAIN(true, true, true); else MT_PLAIN(true, true, false); }
+        else { if (tr) MT_PLAIN(true, false, true); else MT_PLAIN(true, false, false); }
+    } else {
+        if (ck) { if (tr) MT_PLAIN(false, true, true); else MT_PLAIN(false, true, false); }
+        else { if (tr) MT_PLAIN(false, false, true); else MT_PLAIN(false, false, false); }
+    }
+#undef MT_PLAIN
     return hipGetLastError();
+}
+
+static const void *persistent_fn(bool map, bool trace) {
+    if (map) return trace ? reinterpret_cast<const void *>(k_persistent<true, true>)
+                          : reinterpret_cast<const void *>(k_persistent<true, false>);
+    return trace ? reinterpret_cast<const void *>(k_persistent<false, true>)
+                 : reinterpret_cast<const void *>(k_persistent<false, false>);
 }
 
 int persistent_blocks_per_cu(const Tables &T, int block) {
     int n = 0;
-    const bool map = T.field.map != nullptr;
-    hipError_t e = map ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &n, reinterpret_cast<const void *>(k_persistent<true>), block, T.lds.bytes)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &n, reinterpret_cast<const void *>(k_persistent<false>), block, T.lds.bytes);
+    // The register footprint of the trace-free form sets the grid.
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, persistent_fn(T.field.map != nullptr, false), block, T.lds.bytes);
     if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
@@ -884,10 +1025,13 @@ hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, 
                              hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
     const size_t shm = (size_t)T.lds.bytes;
-    if (T.field.map != nullptr)
-        hipLaunchKernelGGL((k_persistent<true>), dim3(grid), dim3(block), shm, s, T, R, io, compact_every, queue);
-    else
-        hipLaunchKernelGGL((k_persistent<false>), dim3(grid), dim3(block), shm, s, T, R, io, compact_every, queue);
+    const bool map = T.field.map != nullptr, tr = R.n_trace > 0;
+#define MT_PERS(A, B) \
+    hipLaunchKernelGGL((k_persistent<A, B>), dim3(grid), dim3(block), shm, s, T, R, io, \
+                       compact_every, queue)
+    if (map) { if (tr) MT_PERS(true, true); else MT_PERS(true, false); }
+    else { if (tr) MT_PERS(false, true); else MT_PERS(false, false); }
+#undef MT_PERS
     return hipGetLastError();
 }
 
@@ -899,10 +1043,15 @@ hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n
     return hipGetLastError();
 }
 
+static bool adjoint_lds_history(const Tables &T) {
+    if (T.field.map != nullptr) return false;
+    const char *env = getenv("MT_ADJOINT_HISTORY");
+    return !(env && env[0] == 'g');   // "global": keep the history in device memory
+}
+
 int64_t adjoint_scratch_bytes(const Tables &T, int64_t lanes) {
-    int64_t b = (int64_t)kCkptEvery * 3 * sizeof(float) * lanes;
-    if (T.field.map != nullptr) b += (int64_t)kCkptEvery * 3 * sizeof(double) * lanes;
-    return b;
+    if (adjoint_lds_history(T)) return 0;
+    return (int64_t)kCkptEvery * (3 * sizeof(float) + 3 * sizeof(double)) * lanes;
 }
 
 hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
@@ -910,13 +1059,17 @@ hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
                           int block, hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
     const int64_t grid = (R.lanes + block - 1) / block;
-    const size_t shm = (size_t)((T.lds.bytes + 15) & ~15) +
-                       (size_t)T.geom.n_mag * block * sizeof(double);
+    const bool map = T.field.map != nullptr;
+    const bool ldsh = adjoint_lds_history(T);
+    size_t shm = (size_t)((T.lds.bytes + 15) & ~15) + (size_t)T.geom.n_mag * block * sizeof(double);
+    if (ldsh) shm += (size_t)kCkptEvery * 3 * block * sizeof(float);
     char *sc = reinterpret_cast<char *>(scratch);
-    if (T.field.map != nullptr)
-        hipLaunchKernelGGL((k_adjoint<true>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
+    if (map)
+        hipLaunchKernelGGL((k_adjoint<true, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
+    else if (ldsh)
+        hipLaunchKernelGGL((k_adjoint<false, true>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
     else
-        hipLaunchKernelGGL((k_adjoint<false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
+        hipLaunchKernelGGL((k_adjoint<false, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
     return hipGetLastError();
 }
 

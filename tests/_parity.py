@@ -126,8 +126,13 @@ def compare(gpu, ora, sel=None, trace_rows=0, max_tie_frac=0.01, label=""):
     dr = np.linalg.norm(st_g[:3] - ora.state[:3], axis=0)
     dp = np.linalg.norm(st_g[3:] - ora.state[3:], axis=0)
     ps = np.linalg.norm(ora.state[3:], axis=0)
+    rel_dp = np.where(valid, dp / np.where(ps > 0, ps, 1), 0)
     stats = {"n": n, "tie": int(tie.sum()),
              "max_abs_dr": float(np.where(valid, dr, 0).max()) if n else 0.0,
-             "max_rel_dp": float(np.where(valid, dp / np.where(ps > 0, ps, 1), 0).max()) if n else 0.0}
+             "max_rel_dp": float(rel_dp.max()) if n else 0.0}
+    if n:
+        w = int(np.argmax(rel_dp))
+        stats["worst"] = {"status": int(ora.status[w]), "n_steps": int(ora.n_steps[w]),
+                          "p_final": float(ps[w])}
     assert tie.mean() <= max_tie_frac if n else True, f"{label}: {tie.sum()} of {n} muons diverged"
     return stats

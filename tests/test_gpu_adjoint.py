@@ -110,12 +110,17 @@ def test_adjoint_inputs_vs_oracle_fd(torch):
 
 def test_adjoint_with_field_map_inputs(torch):
     """Shield geometry (trilinear map, several materials): gradients with
-    respect to the initial state through the map's spatial derivative."""
+    respect to the initial state through the map's spatial derivative.
+
+    The trilinear field is only piecewise smooth (its gradient jumps at cell
+    faces, 4 cm apart), so the h = 1e-3 Richardson reference is not valid here;
+    the reference is a plain central difference with h = 1e-5 m (GeV/c), whose
+    truncation error is negligible and which straddles a cell face on only a
+    small fraction of steps."""
     wl = W.make_workload("shield", n_muons=400, n_fill=200_000)
     idx = np.arange(400)
-    kw = dict(z_det=35.0)
     comps = (0, 1, 3, 4)
-    ref, d1, flag = _richardson(lambda h: oracle.fd_inputs(wl, idx, h=h, comps=comps, **kw), 1e-3)
+    ref, flag = oracle.fd_inputs(wl, idx, h=1e-5, comps=comps, z_det=35.0)
     g, _, status, _ = _gpu_grads(torch, wl, idx, mask=~flag, z_det=35.0)
     keep = (~flag) & (status == 2)
     assert keep.sum() > 20

@@ -115,7 +115,7 @@ def test_invalid_and_degenerate_inputs():
     # step cap
     wl0 = CU.workload(hist, geom, mu, p_min=0.5, max_steps=0)
     g0 = gpu_run(wl0)
-    assert g0["status"][0] == oracle.ST_MAXSTEPS and g0["n_steps"][0] == 0
+    assert g0["status"][0] == oracle.ST_STEPS and g0["n_steps"][0] == 0
 
 
 def test_empty_launch():
