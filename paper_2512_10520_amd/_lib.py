@@ -9,7 +9,9 @@ import os
 import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmt.so")
+# MT_LIBRARY points at another build of the same library (e.g. to compare two
+# builds on one machine); by default the in-tree build is used.
+LIB_PATH = os.environ.get("MT_LIBRARY") or os.path.join(_HERE, "libmt.so")
 
 MT_OK = 0
 ERRORS = {-1: "MT_ERR_INVALID_ARG", -2: "MT_ERR_SHAPE", -3: "MT_ERR_EMPTY_HIST",

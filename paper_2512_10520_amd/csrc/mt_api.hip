@@ -632,7 +632,7 @@ int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in
     }
     if ((rc = g.scratch.ensure((size_t)mt::adjoint_scratch_bytes(g.T, c.lanes)))) return rc;
     if ((rc = g.gs_lane.ensure((size_t)std::max(1, n_mag) * c.lanes * sizeof(double)))) return rc;
-    const int block = std::getenv("MT_ADJOINT_BLOCK") ? std::atoi(std::getenv("MT_ADJOINT_BLOCK")) : 128;
+    const int block = std::getenv("MT_ADJOINT_BLOCK") ? std::atoi(std::getenv("MT_ADJOINT_BLOCK")) : 64;
     if (block < 64 || block > 256 || block % 64)
         return fail(MT_ERR_INVALID_ARG, "MT_ADJOINT_BLOCK must be 64, 128, 192 or 256");
     MT_HIP(mt::launch_adjoint(g.T, c.R, c.io, g_out, g_in,

@@ -135,6 +135,8 @@ __device__ __forceinline__ Lds stage_tables(char *smem, const Tables &T) {
 // ---------------------------------------------------------------------------
 struct Lane {
     double x, y, z, px, py, pz;
+    double zlo, zhi;
+    double e2lo, e2hi;
     float q;
     float bx, by, bz;     // scaled field of box bvol
     int32_t k, status, ibin, slab, vol, bvol, var;
@@ -145,7 +147,11 @@ struct Lane {
 __device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, const DevRun &R) {
     int64_t var = 0, j = g;
     if (R.lanes != R.n) {
-        var = g / R.n;
+        if (R.lanes <= 0xFFFFFFFFll) {
+            var = (uint32_t)g / (uint32_t)R.n;
+        } else {
+            var = g / R.n;
+        }
         j = g - var * R.n;
     }
     L.x = io.x[j];
@@ -165,6 +171,10 @@ __device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, c
     L.vol = -1;
     L.bvol = -2;
     L.bx = L.by = L.bz = 0.0f;
+    L.zlo = INFINITY;
+    L.zhi = -INFINITY;
+    L.e2lo = INFINITY;
+    L.e2hi = -INFINITY;
     L.status = MT_ST_RUNNING;
     const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
     const bool ok = isfinite(L.x) && isfinite(L.y) && isfinite(L.z) && isfinite(p2) &&
@@ -207,9 +217,11 @@ __device__ __forceinline__ int find_box(const Lds &S, int s, double x, double y)
 // Box containing the lane's position (lowest index), using the cached slab
 // and, for geometries without overlapping boxes, the cached box.
 __device__ __forceinline__ int locate(Lane &L, const Tables &T, const Lds &S) {
-    const bool same_slab = L.slab >= 0 && L.z >= S.slabz[L.slab] && L.z < S.slabz[L.slab + 1];
+    const bool same_slab = L.z >= L.zlo && L.z < L.zhi;
     if (!same_slab) {
         L.slab = find_slab(S, T.geom.n_slab, L.z, L.slab);
+        L.zlo = S.slabz[L.slab];
+        L.zhi = S.slabz[L.slab + 1];
     } else if (L.vol >= 0 && T.geom.disjoint && in_box_xy(S, L.vol, L.x, L.y)) {
         return L.vol;
     }
@@ -234,7 +246,13 @@ __device__ __forceinline__ int find_bin(const Lds &S, int P, double p2, int i) {
 }
 
 __device__ __forceinline__ int bin_of(Lane &L, const Tables &T, const Lds &S, double p2) {
-    L.ibin = find_bin(S, T.hist.n_pbin, p2, L.ibin);
+    if (!(p2 >= L.e2lo && p2 < L.e2hi)) {
+        const int P = T.hist.n_pbin;
+        const int i = find_bin(S, P, p2, L.ibin);
+        L.ibin = i;
+        L.e2lo = i > 0 ? S.e2[i] : -INFINITY;
+        L.e2hi = i < P - 1 ? S.e2[i + 1] : INFINITY;
+    }
     return L.ibin;
 }
 
@@ -444,11 +462,11 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
     st = (fabs(L.x) >= T.geom.x_max) ? MT_ST_XMAX : st;
     st = (L.z >= T.geom.z_max) ? MT_ST_ZMAX : st;
     st = (p2 < R.pmin2) ? MT_ST_PMIN : st;
-    if (st != MT_ST_RUNNING) {
+    const int vol = locate(L, T, S);
+    if (st != MT_ST_RUNNING) {       // the muon stops here; vol is its final volume
         L.status = st;
         return false;
     }
-    const int vol = locate(L, T, S);
     const int mat = vol >= 0 ? S.mat[vol] : -1;
     float ux = 0.0f, uy = 0.0f, uz = 0.0f;
     int cell = -1;
@@ -515,12 +533,7 @@ __device__ __forceinline__ void store_lane(const Lane &L, const Tables &T, const
     io.opz[g] = L.pz;
     io.status[g] = L.status;
     io.n_steps[g] = L.k;
-    int vol = -1;
-    if (L.status != MT_ST_INVALID) {
-        const int s = find_slab(S, T.geom.n_slab, L.z, L.slab);
-        vol = find_box(S, s, L.x, L.y);
-    }
-    io.volume[g] = vol;
+    io.volume[g] = L.status == MT_ST_INVALID ? -1 : L.vol;
 }
 
 __device__ __forceinline__ void write_ckpt(const Lane &L, const DevRun &R) {
@@ -555,50 +568,118 @@ __global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form: a resident grid pulls muons from an atomic queue.  Every
-// `compact` steps each wave writes out its finished muons and refills those
-// lanes with the next queue entries (ballot + prefix count), so waves stay
-// full while trajectory lengths differ.  Results are bit-identical to the
-// plain form because the random stream is keyed by (muon, step), not by lane.
-// A wave exits once the queue is exhausted and all of its lanes are idle.
+// Persistent form with block-level stream compaction.  A resident grid pulls
+// batches of blockDim muons from an atomic queue.  The muons of a batch step
+// in lockstep (so lanes of a wave stay at the same z and take the same
+// branches); every `compact` steps the block packs its surviving muons into
+// its lowest lanes through LDS, and waves left without a muon skip the steps
+// until the batch is done, so the issue slots go to busy waves.  When a batch
+// is exhausted the block takes the next one; it exits when the queue is.
+// Results are bit-identical to the plain form: the random stream is keyed by
+// (muon, step), the state moves exactly, and the lookup caches are rebuilt.
 // ---------------------------------------------------------------------------
+struct MoveRec {                // one muon in flight, 64 bytes
+    double x, y, z, px, py, pz;
+    int64_t g;
+    int32_t ibin_slab;          // ibin (low 16 bits) | slab (high 16 bits)
+    int32_t q_vol;              // charge (low 8 bits, signed) | volume + 1 (next 8 bits)
+};
+
+__device__ __forceinline__ void pack_rec(const Lane &L, MoveRec &m) {
+    m.x = L.x;
+    m.y = L.y;
+    m.z = L.z;
+    m.px = L.px;
+    m.py = L.py;
+    m.pz = L.pz;
+    m.g = L.g;
+    m.ibin_slab = (L.ibin & 0xFFFF) | (L.slab << 16);
+    m.q_vol = ((int)L.q & 0xFF) | ((L.vol + 1) << 8);
+}
+
+__device__ __forceinline__ void unpack_rec(Lane &L, const MoveRec &m, int32_t k, const DevRun &R) {
+    L.x = m.x;
+    L.y = m.y;
+    L.z = m.z;
+    L.px = m.px;
+    L.py = m.py;
+    L.pz = m.pz;
+    L.g = m.g;
+    L.ibin = (int16_t)(m.ibin_slab & 0xFFFF);
+    L.slab = m.ibin_slab >> 16;
+    L.q = (float)(int8_t)(m.q_vol & 0xFF);
+    L.vol = ((m.q_vol >> 8) & 0xFF) - 1;
+    int64_t var = 0, j = L.g;
+    if (R.lanes != R.n) {
+        var = R.lanes <= 0xFFFFFFFFll ? (int64_t)((uint32_t)L.g / (uint32_t)R.n) : L.g / R.n;
+        j = L.g - var * R.n;
+    }
+    L.var = (int32_t)var;
+    L.ph = philox_prefix((uint32_t)j, (uint32_t)((uint64_t)j >> 32), R.key0, R.key1);
+    L.k = k;
+    L.status = MT_ST_RUNNING;
+    L.bvol = -2;                // caches are rebuilt from the moved hints
+    L.zlo = INFINITY;
+    L.zhi = -INFINITY;
+    L.e2lo = INFINITY;
+    L.e2hi = -INFINITY;
+}
+
 template <bool MAP, bool TRACE>
 __global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO io, int compact,
                                                      unsigned long long *queue) {
     extern __shared__ __align__(16) char smem[];
+    __shared__ unsigned long long batch_base;
+    __shared__ int wave_count[1024 / kWave];
     const Lds S = stage_tables(smem, T);
+    MoveRec *recs = reinterpret_cast<MoveRec *>(smem + ((T.lds.bytes + 15) & ~15));
     const StepConst sc = step_const(R);
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    Lane L;
-    L.status = MT_ST_INVALID;
-    bool active = false, exhausted = false;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+    const int n_waves = blockDim.x / kWave;
     for (;;) {
-        const uint64_t empty = __ballot(!active);
-        if (!exhausted && empty != 0ull) {
-            const uint32_t n_empty = (uint32_t)__popcll(empty);
-            unsigned long long base = 0ull;
-            if (lane == 0) base = atomicAdd(queue, (unsigned long long)n_empty);
-            base = __shfl(base, 0);
-            if (!active) {
-                const unsigned long long g = base + (unsigned long long)__popcll(empty & below);
-                if (g < (unsigned long long)R.lanes) {
-                    load_lane(L, (int64_t)g, io, R);
-                    if (L.status == MT_ST_RUNNING) active = true;
-                    else store_lane(L, T, S, io);
+        if (tid == 0) batch_base = atomicAdd(queue, (unsigned long long)blockDim.x);
+        __syncthreads();
+        const unsigned long long base = batch_base;
+        if (base >= (unsigned long long)R.lanes) break;          // the same for the whole block
+        Lane L;
+        bool active = false;
+        const unsigned long long gg = base + (unsigned long long)tid;
+        if (gg < (unsigned long long)R.lanes) {
+            load_lane(L, (int64_t)gg, io, R);
+            if (L.status == MT_ST_RUNNING) active = true;
+            else store_lane(L, T, S, io);
+        }
+        int n_busy = blockDim.x;        // lanes [0, n_busy) may hold a muon
+        int32_t k_done = 0;             // steps taken by every muon still in the batch
+        for (;;) {
+            if (wave * kWave < n_busy) {
+                for (int c = 0; c < compact; ++c) {
+                    if (active && !advance<MAP, false, TRACE>(L, T, S, R, sc)) {
+                        store_lane(L, T, S, io);
+                        active = false;
+                    }
                 }
             }
-            if (base + n_empty >= (unsigned long long)R.lanes) exhausted = true;
-        }
-        if (__ballot(active) == 0ull) {
-            if (exhausted) break;
-            continue;
-        }
-        for (int c = 0; c < compact; ++c) {
-            if (active && !advance<MAP, false, TRACE>(L, T, S, R, sc)) {
-                store_lane(L, T, S, io);
-                active = false;
+            k_done += compact;
+            // pack the survivors into lanes [0, total)
+            const uint64_t m = __ballot(active);
+            if (lane == 0) wave_count[wave] = (int)__popcll(m);
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int w = 0; w < n_waves; ++w) {
+                const int cnt = wave_count[w];
+                before += (w < wave) ? cnt : 0;
+                total += cnt;
             }
+            const int rank = before + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (active) pack_rec(L, recs[rank]);
+            __syncthreads();
+            active = tid < total;
+            if (active) unpack_rec(L, recs[tid], k_done, R);
+            n_busy = total;
+            __syncthreads();            // records and counts are rewritten next round
+            if (total == 0) break;
         }
     }
 }
@@ -1004,6 +1085,10 @@ hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int b
     return hipGetLastError();
 }
 
+static size_t persistent_lds(const Tables &T, int block) {
+    return (size_t)((T.lds.bytes + 15) & ~15) + (size_t)block * sizeof(MoveRec);
+}
+
 static const void *persistent_fn(bool map, bool trace) {
     if (map) return trace ? reinterpret_cast<const void *>(k_persistent<true, true>)
                           : reinterpret_cast<const void *>(k_persistent<true, false>);
@@ -1015,7 +1100,7 @@ int persistent_blocks_per_cu(const Tables &T, int block) {
     int n = 0;
     // The register footprint of the trace-free form sets the grid.
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, persistent_fn(T.field.map != nullptr, false), block, T.lds.bytes);
+        &n, persistent_fn(T.field.map != nullptr, false), block, persistent_lds(T, block));
     if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
@@ -1024,7 +1109,7 @@ hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, 
                              int grid, int compact_every, unsigned long long *queue,
                              hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
-    const size_t shm = (size_t)T.lds.bytes;
+    const size_t shm = persistent_lds(T, block);
     const bool map = T.field.map != nullptr, tr = R.n_trace > 0;
 #define MT_PERS(A, B) \
     hipLaunchKernelGGL((k_persistent<A, B>), dim3(grid), dim3(block), shm, s, T, R, io, \
@@ -1043,10 +1128,13 @@ hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n
     return hipGetLastError();
 }
 
+// Where the adjoint keeps a segment's start states: device memory (default;
+// at 16 steps x 12 B per lane it stays L2/Infinity-Cache resident and leaves
+// LDS free for occupancy) or LDS (MT_ADJOINT_HISTORY=lds, no field map).
 static bool adjoint_lds_history(const Tables &T) {
     if (T.field.map != nullptr) return false;
     const char *env = getenv("MT_ADJOINT_HISTORY");
-    return !(env && env[0] == 'g');   // "global": keep the history in device memory
+    return env && env[0] == 'l';
 }
 
 int64_t adjoint_scratch_bytes(const Tables &T, int64_t lanes) {
