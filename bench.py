@@ -28,12 +28,16 @@ METRIC = "muon-steps/sec on 1 MI355X vs CPU FP64 oracle; fwd+adjoint time per de
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12
 
-# Algorithmic operations of one muon step, counted from the method (the design doc
-# lists them): break test 10, box lookup 8, momentum bin 4, Philox4x32-10 100,
-# inverse CDF 6, jitter + azimuth 12, kick + rotation 30, field 6, RK4 110,
-# FP64 accumulation 12.
-OPS_PER_MATERIAL_STEP = 298
-OPS_PER_VACUUM_STEP = 298 - (4 + 100 + 6 + 12 + 30)
+# Algorithmic operations of one muon step, counted from the method at the
+# granularity of single hardware operations (the design doc lists them): break
+# test 8, box lookup 6, momentum bin 2, Philox4x32-10 53 (18 32x32->64
+# products + 35 xors once the muon-constant part of rounds 1-2 is hoisted),
+# inverse CDF 7, cell split 3, jitter + azimuth 18, kick + rotation 30,
+# field 1, RK4 with FP64 accumulation 103, loop 2 -> 233 for a material step;
+# a vacuum step in zero field is 40.  The field map adds 30 (8 corner loads,
+# 21 lerps, index arithmetic); zero-field material steps replace the RK4 by
+# the straight-line update (-84).
+OPS = {"material": 233, "vacuum": 40, "map": 30, "straight": -84}
 
 WORKLOADS = {
     "tiny": "tiny: 1 iron box 1 m, no field, 32x64x64 histograms, 10^4 muons at 100 GeV",
@@ -52,7 +56,7 @@ def _parse():
     ap.add_argument("--mode", default="auto", choices=["auto", "plain", "persistent"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-design", action="store_true")
-    ap.add_argument("--cpu-muons", type=int, default=400_000)
+    ap.add_argument("--cpu-muons", type=int, default=1_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     return ap.parse_args()
@@ -138,18 +142,13 @@ def main():
     wall, ev_ms = _time_launches(lambda: api.propagate(dm, sp, scales=scales, out=out),
                                  args.steps, torch)
     value = steps_per_pass * args.steps / wall
-    # Algorithmic ALU work per pass from the material/vacuum step split.
-    if args.config in ("block", "scan"):
-        vac_steps = int(out.n_steps.numel())           # the first step starts before the box
-    else:
-        vac_steps = 0
-    mat_steps = steps_per_pass - vac_steps
-    alg_ops = mat_steps * OPS_PER_MATERIAL_STEP + vac_steps * OPS_PER_VACUUM_STEP
+    alg_ops = algorithmic_ops(args.config, steps_per_pass, int(out.n_steps.numel()))
     achieved = alg_ops / (ev_ms * 1e-3)
+    kernel = "k_persistent" if mode == "persistent" else "k_plain"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
                 "unit": "Tops/s (VALU lane-ops)", "frac": achieved / VALU_LANE_OPS_PEAK,
-                "traffic": None, "kernel": "k_persistent" if mode == "persistent" else "k_plain",
-                "kernel_ms": ev_ms}
+                "traffic": measured_traffic(kernel, args.config), "kernel": kernel,
+                "kernel_ms": ev_ms, "ops_per_pass": alg_ops}
     line = {"metric": METRIC, "value": value, "unit": "muon-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -159,12 +158,66 @@ def main():
                        "mode": mode, "mode_probe_ms": probe, "autotune": tuned},
             "roofline": roofline}
 
+    if args.config == "scan":
+        line["config"]["per_variant_plain_ms"] = per_variant_plain(api, dm, wl, scales, torch)
+
     if not args.no_design and args.config == "block":
         line["design_step"] = design_step(api, W, torch)
 
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_muons)
     print(json.dumps(line), flush=True)
+
+
+def per_variant_plain(api, dm, wl, scales, torch, reps=2):
+    """The scan as 64 separate plain launches (one per field-scale variant),
+    the form a caller without the batched launch would use."""
+    v = wl.run.n_variants
+    spec = api.RunSpec.from_workload(wl, mode="plain")
+    spec.n_variants = 1
+    out = api.alloc_result(spec, len(dm), "cuda")
+    rows = [scales[i:i + 1].contiguous() for i in range(v)]
+
+    def one_scan():
+        for i in range(v):
+            api.propagate(dm, spec, scales=rows[i], out=out)
+
+    one_scan()
+    _, ms = _time_launches(one_scan, reps, torch)
+    return ms
+
+
+def algorithmic_ops(config, steps, lanes):
+    """Algorithmic operations of one pass (see OPS).  block/scan/diff: the
+    first step of every muon starts in vacuum before the box; tiny: zero
+    field; shield: every step is counted as a material step with a map
+    lookup (an upper bound: the air gaps are vacuum)."""
+    if config in ("block", "scan", "diff"):
+        return (steps - lanes) * OPS["material"] + lanes * OPS["vacuum"]
+    if config == "tiny":
+        return (steps - lanes) * (OPS["material"] + OPS["straight"]) + lanes * OPS["vacuum"]
+    return steps * (OPS["material"] + OPS["map"])
+
+
+def measured_traffic(kernel, config):
+    """HBM bytes per launch of this kernel on this workload, from the counter
+    summary under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy
+    of known size), or None if there is none or the kernel source changed
+    since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_counters.md")
+    src = os.path.join(ROOT, "paper_2512_10520_amd", "csrc", "mt_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and " = " in line:
+            k, v = line[2:].split(" = ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def design_step(api, W, torch, reps=3):
