@@ -410,41 +410,52 @@ struct StepConst {
     float h, h2, h6, h3;   // d, d/2, d/6, d/3
 };
 
-__device__ __forceinline__ void rk4(Lane &L, float3 B, const StepConst &c) {
-    const float3 a0 = make_float3((float)L.px, (float)L.py, (float)L.pz);
+__device__ __forceinline__ float3 stage0(const Lane &L) {
+    return make_float3((float)L.px, (float)L.py, (float)L.pz);
+}
+
+// a0 must be stage0(L) (the FP32 momentum the stages start from).
+__device__ __forceinline__ void rk4_from(Lane &L, float3 a0, float3 B, const StepConst &c) {
     const float r0 = __builtin_amdgcn_rsqf(norm2(a0));
     const float3 n0 = scale3(r0, a0);
+    float drx, dry, drz;
     if (B.x == 0.0f && B.y == 0.0f && B.z == 0.0f) {
-        L.x += (double)(c.h * n0.x);
-        L.y += (double)(c.h * n0.y);
-        L.z += (double)(c.h * n0.z);
-        return;
+        drx = c.h * n0.x;
+        dry = c.h * n0.y;
+        drz = c.h * n0.z;
+    } else {
+        const float kq = (float)kKappa * L.q;
+        const float3 cb = scale3(kq, B);
+        const float3 k1 = cross3(n0, cb);
+        const float3 a1 = axpy(c.h2, k1, a0);
+        const float3 n1 = scale3(__builtin_amdgcn_rsqf(norm2(a1)), a1);
+        const float3 k2 = cross3(n1, cb);
+        const float3 a2 = axpy(c.h2, k2, a0);
+        const float3 n2 = scale3(__builtin_amdgcn_rsqf(norm2(a2)), a2);
+        const float3 k3 = cross3(n2, cb);
+        const float3 a3 = axpy(c.h, k3, a0);
+        const float3 n3 = scale3(__builtin_amdgcn_rsqf(norm2(a3)), a3);
+        const float3 k4 = cross3(n3, cb);
+        // h/6 (v1 + 2 v2 + 2 v3 + v4)
+        drx = c.h6 * (fmaf(2.0f, n1.x + n2.x, n0.x) + n3.x);
+        dry = c.h6 * (fmaf(2.0f, n1.y + n2.y, n0.y) + n3.y);
+        drz = c.h6 * (fmaf(2.0f, n1.z + n2.z, n0.z) + n3.z);
+        const float dpx = c.h6 * (fmaf(2.0f, k2.x + k3.x, k1.x) + k4.x);
+        const float dpy = c.h6 * (fmaf(2.0f, k2.y + k3.y, k1.y) + k4.y);
+        const float dpz = c.h6 * (fmaf(2.0f, k2.z + k3.z, k1.z) + k4.z);
+        L.px += (double)dpx;
+        L.py += (double)dpy;
+        L.pz += (double)dpz;
     }
-    const float kq = (float)kKappa * L.q;
-    const float3 cb = scale3(kq, B);
-    const float3 k1 = cross3(n0, cb);
-    const float3 a1 = axpy(c.h2, k1, a0);
-    const float3 n1 = scale3(__builtin_amdgcn_rsqf(norm2(a1)), a1);
-    const float3 k2 = cross3(n1, cb);
-    const float3 a2 = axpy(c.h2, k2, a0);
-    const float3 n2 = scale3(__builtin_amdgcn_rsqf(norm2(a2)), a2);
-    const float3 k3 = cross3(n2, cb);
-    const float3 a3 = axpy(c.h, k3, a0);
-    const float3 n3 = scale3(__builtin_amdgcn_rsqf(norm2(a3)), a3);
-    const float3 k4 = cross3(n3, cb);
-    // h/6 (v1 + 2 v2 + 2 v3 + v4)
-    const float drx = c.h6 * (fmaf(2.0f, n1.x + n2.x, n0.x) + n3.x);
-    const float dry = c.h6 * (fmaf(2.0f, n1.y + n2.y, n0.y) + n3.y);
-    const float drz = c.h6 * (fmaf(2.0f, n1.z + n2.z, n0.z) + n3.z);
-    const float dpx = c.h6 * (fmaf(2.0f, k2.x + k3.x, k1.x) + k4.x);
-    const float dpy = c.h6 * (fmaf(2.0f, k2.y + k3.y, k1.y) + k4.y);
-    const float dpz = c.h6 * (fmaf(2.0f, k2.z + k3.z, k1.z) + k4.z);
+    // the position update is shared by both branches (keeps every Lane field
+    // in registers: no store through a selected address)
     L.x += (double)drx;
     L.y += (double)dry;
     L.z += (double)drz;
-    L.px += (double)dpx;
-    L.py += (double)dpy;
-    L.pz += (double)dpz;
+}
+
+__device__ __forceinline__ void rk4(Lane &L, float3 B, const StepConst &c) {
+    rk4_from(L, stage0(L), B, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -713,29 +724,6 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) {
     return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z));
 }
 
-// Post-kick momentum from an FP32 pre-kick momentum (same algebra as kick()).
-__device__ __forceinline__ float3 kick_f32(float3 p, float3 u) {
-    const float p2f = norm2(p);
-    const float rinv = __builtin_amdgcn_rsqf(p2f);
-    const float pm = p2f * rinv;
-    const float nx = p.x * rinv, ny = p.y * rinv, nz = p.z * rinv;
-    const float dx = pm * u.x, dy = pm * u.y;
-    const float opc = 1.0f + nz;
-    float tx, ty, tz;
-    if (opc > 0.0f) {
-        const float coef = fmaf(nx, dy, -ny * dx) * __builtin_amdgcn_rcpf(opc);
-        tx = fmaf(nz, dx, -coef * ny);
-        ty = fmaf(nz, dy, coef * nx);
-        tz = -fmaf(nx, dx, ny * dy);
-    } else {
-        tx = dx;
-        ty = -dy;
-        tz = 0.0f;
-    }
-    const float keep = 1.0f + u.z;
-    return make_float3(fmaf(p.x, keep, tx), fmaf(p.y, keep, ty), fmaf(p.z, keep, tz));
-}
-
 // Gradient of l . g_u(p) with g_u(p) = p_z u + A x u + (A.u) A / (|p| + p_z),
 // A = (-p_y, p_x, 0): the kick is p -> p + g_u(p).
 __device__ __forceinline__ float3 kick_adjoint_corr(float3 p, float3 u, float3 l) {
@@ -775,12 +763,12 @@ __device__ __forceinline__ float3 map_grad_t(const DevField &F, const Corner8 &c
 // rz) its position (used only with a field map).
 template <bool MAP>
 __device__ __forceinline__ void reverse_step(const Tables &T, const Lds &S, const DevRun &R,
-                                             const StepConst &sc, float kq, int var, float3 p0,
+                                             const StepConst &sc, float kq, float3 p0, float3 a0,
                                              double rx, double ry, double rz, int vol, float3 u,
-                                             double lr[3], double lp[3], double *sgs, int bd) {
+                                             float3 Bbox, double lr[3], double lp[3], double *sgs,
+                                             int bd) {
     const int mat = vol >= 0 ? S.mat[vol] : -1;
-    const float3 a0 = mat >= 0 ? kick_f32(p0, u) : p0;
-    const float3 B = field_at<MAP>(T, S, R, vol, var, rx, ry, rz);
+    const float3 B = add_map<MAP>(T, Bbox, rx, ry, rz);
     const float3 Lr = make_float3((float)lr[0], (float)lr[1], (float)lr[2]);
     const float3 Lp = make_float3((float)lp[0], (float)lp[1], (float)lp[2]);
     // RK4 stages of the step (the straight-line shortcut of the forward pass
@@ -852,19 +840,29 @@ __device__ __forceinline__ void reverse_step(const Tables &T, const Lds &S, cons
 }
 
 // Re-run one step of a segment with its recorded kick and volume (the
-// arithmetic of advance(), so the same bits).
+// arithmetic of advance(), so the same bits).  B caches the field of volume
+// bvol.  Returns the FP32 momentum the RK4 stages started from.
 template <bool MAP>
-__device__ __forceinline__ void replay_step(Lane &L, const Tables &T, const Lds &S,
-                                            const DevRun &R, const StepConst &sc, int var,
-                                            float4 rec) {
+__device__ __forceinline__ float3 replay_step(Lane &L, const Tables &T, const Lds &S,
+                                              const DevRun &R, const StepConst &sc, int var,
+                                              float4 rec) {
     const int vol = __float_as_int(rec.w);
     const int mat = vol >= 0 ? S.mat[vol] : -1;
     if (mat >= 0) {
         const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
         kick(L, p2, rec.x, rec.y, rec.z);
     }
-    const float3 B = field_at<MAP>(T, S, R, vol, var, L.x, L.y, L.z);
-    rk4(L, B, sc);
+    if (vol != L.bvol) {
+        const float3 b = box_field(T, S, R, vol, var);
+        L.bx = b.x;
+        L.by = b.y;
+        L.bz = b.z;
+        L.bvol = vol;
+    }
+    const float3 B = add_map<MAP>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
+    const float3 a0 = stage0(L);
+    rk4_from(L, a0, B, sc);
+    return a0;
 }
 
 // The segment's start momenta are kept either in LDS (LDSH) or in a per-lane
@@ -912,59 +910,61 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
             L.q = q;
             // kick records of the segment: one float4 per (step, lane)
             const float4 *rec = reinterpret_cast<const float4 *>(R.tape) + (size_t)k0 * lanes + g;
+            L.bvol = -2;
+            // history of the segment: p0 (pre-kick) and a0 (stage-0) momenta
+            // per step, [step][6][lane] in LDS (LDSH) or device memory
+            float *hp;
+            int64_t hs;
             if (LDSH) {
-                // history[i][c][tid] in LDS, after the staged tables and the
-                // per-lane scale-gradient accumulators
-                float4 next = rec[0];
-                for (int k = k0; k < k1; ++k) {
-                    const float4 cur = next;
-                    if (k + 1 < k1) next = rec[(size_t)(k + 1 - k0) * lanes];
-                    float *h = hist + (size_t)(k - k0) * 3 * bd;
-                    h[0] = (float)L.px;
-                    h[bd] = (float)L.py;
-                    h[2 * bd] = (float)L.pz;
-                    replay_step<MAP>(L, T, S, R, sc, var, cur);
-                }
-                next = rec[(size_t)(k1 - 1 - k0) * lanes];
-                for (int k = k1 - 1; k >= k0; --k) {
-                    const float4 cur = next;
-                    if (k > k0) next = rec[(size_t)(k - 1 - k0) * lanes];
-                    const float *h = hist + (size_t)(k - k0) * 3 * bd;
-                    reverse_step<MAP>(T, S, R, sc, kq, var, make_float3(h[0], h[bd], h[2 * bd]),
-                                      0.0, 0.0, 0.0, __float_as_int(cur.w),
-                                      make_float3(cur.x, cur.y, cur.z), lr, lp, sgs, bd);
-                }
+                hp = hist;
+                hs = bd;
             } else {
-                float *hp = reinterpret_cast<float *>(scratch);
-                double *hr = reinterpret_cast<double *>(
-                    scratch + (size_t)kCkptEvery * 3 * sizeof(float) * lanes);
-                for (int k = k0; k < k1; ++k) {
-                    float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
-                    h[0] = (float)L.px;
-                    h[lanes] = (float)L.py;
-                    h[2 * lanes] = (float)L.pz;
-                    if (MAP) {
-                        double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
-                        hh[0] = L.x;
-                        hh[lanes] = L.y;
-                        hh[2 * lanes] = L.z;
-                    }
-                    replay_step<MAP>(L, T, S, R, sc, var, rec[(size_t)(k - k0) * lanes]);
+                hp = reinterpret_cast<float *>(scratch) + g;
+                hs = lanes;
+            }
+            double *hr = reinterpret_cast<double *>(
+                scratch + (size_t)kCkptEvery * 6 * sizeof(float) * lanes) + g;
+            float4 next = rec[0];
+            for (int k = k0; k < k1; ++k) {
+                const float4 cur = next;
+                if (k + 1 < k1) next = rec[(size_t)(k + 1 - k0) * lanes];
+                float *h = hp + (size_t)(k - k0) * 6 * hs;
+                h[0] = (float)L.px;
+                h[hs] = (float)L.py;
+                h[2 * hs] = (float)L.pz;
+                if (MAP) {
+                    double *hh = hr + (size_t)(k - k0) * 3 * lanes;
+                    hh[0] = L.x;
+                    hh[lanes] = L.y;
+                    hh[2 * lanes] = L.z;
                 }
-                for (int k = k1 - 1; k >= k0; --k) {
-                    const float *h = hp + (size_t)(k - k0) * 3 * lanes + g;
-                    double rx = 0.0, ry = 0.0, rz = 0.0;
-                    if (MAP) {
-                        const double *hh = hr + (size_t)(k - k0) * 3 * lanes + g;
-                        rx = hh[0];
-                        ry = hh[lanes];
-                        rz = hh[2 * lanes];
-                    }
-                    const float4 cur = rec[(size_t)(k - k0) * lanes];
-                    reverse_step<MAP>(T, S, R, sc, kq, var, make_float3(h[0], h[lanes], h[2 * lanes]),
-                                      rx, ry, rz, __float_as_int(cur.w),
-                                      make_float3(cur.x, cur.y, cur.z), lr, lp, sgs, bd);
+                const float3 a0 = replay_step<MAP>(L, T, S, R, sc, var, cur);
+                h[3 * hs] = a0.x;
+                h[4 * hs] = a0.y;
+                h[5 * hs] = a0.z;
+            }
+            int bvol = -2;
+            float3 bb = make_float3(0.f, 0.f, 0.f);
+            next = rec[(size_t)(k1 - 1 - k0) * lanes];
+            for (int k = k1 - 1; k >= k0; --k) {
+                const float4 cur = next;
+                if (k > k0) next = rec[(size_t)(k - 1 - k0) * lanes];
+                const float *h = hp + (size_t)(k - k0) * 6 * hs;
+                double rx = 0.0, ry = 0.0, rz = 0.0;
+                if (MAP) {
+                    const double *hh = hr + (size_t)(k - k0) * 3 * lanes;
+                    rx = hh[0];
+                    ry = hh[lanes];
+                    rz = hh[2 * lanes];
                 }
+                const int vol = __float_as_int(cur.w);
+                if (vol != bvol) {
+                    bb = box_field(T, S, R, vol, var);
+                    bvol = vol;
+                }
+                reverse_step<MAP>(T, S, R, sc, kq, make_float3(h[0], h[hs], h[2 * hs]),
+                                  make_float3(h[3 * hs], h[4 * hs], h[5 * hs]), rx, ry, rz, vol,
+                                  make_float3(cur.x, cur.y, cur.z), bb, lr, lp, sgs, bd);
             }
         }
     }
@@ -1138,8 +1138,7 @@ static bool adjoint_lds_history(const Tables &T) {
 }
 
 int64_t adjoint_scratch_bytes(const Tables &T, int64_t lanes) {
-    if (adjoint_lds_history(T)) return 0;
-    return (int64_t)kCkptEvery * (3 * sizeof(float) + 3 * sizeof(double)) * lanes;
+    return (int64_t)kCkptEvery * (6 * sizeof(float) + 3 * sizeof(double)) * lanes;
 }
 
 hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
