@@ -57,6 +57,7 @@ class _Problem(C.Structure):
         ("step", C.c_double), ("max_steps", C.c_int32), ("p_min", C.c_double),
         ("seed", C.c_uint64),
         ("scales", C.c_void_p),
+        ("sampler", C.c_int32),
     ]
 
 
@@ -85,6 +86,11 @@ def lib():
             L.oracle_cdf_t.restype = C.c_uint32
             L.oracle_cdf_cell.argtypes = [C.c_void_p, C.c_int64, C.c_uint32]
             L.oracle_cdf_cell.restype = C.c_int64
+            L.oracle_alias_build.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+            L.oracle_alias_build.restype = C.c_int
+            L.oracle_alias_cell.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32,
+                                            C.c_void_p]
+            L.oracle_alias_cell.restype = C.c_int64
             L.oracle_rotate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
             L.oracle_rk4.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p]
             L.oracle_lookup.argtypes = [C.POINTER(_Problem), C.c_void_p]
@@ -141,6 +147,7 @@ class Problem:
         P.seed = r.seed if seed is None else seed
         sc = r.scales if scales is None else scales
         P.scales = None if sc is None else _ptr(keep(sc, np.float64))
+        P.sampler = int(getattr(r, "sampler", 0))
         self.struct = P
 
 
@@ -220,6 +227,26 @@ def cdf_cells(counts: np.ndarray, t_values: np.ndarray) -> np.ndarray:
         raise ValueError("empty or oversized histogram")
     return np.array([lib().oracle_cdf_cell(cdf.ctypes.data, K, int(t)) for t in t_values],
                     dtype=np.int64)
+
+
+def alias_tables(counts: np.ndarray):
+    """Walker Prob/Alias tables of one histogram: (prob uint32 [K], alias
+    int32 [K]), prob in units of the histogram total."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint32).ravel()
+    K = counts.size
+    prob = np.zeros(K, np.uint32)
+    alias = np.zeros(K, np.int32)
+    rc = lib().oracle_alias_build(counts.ctypes.data, K, prob.ctypes.data, alias.ctypes.data)
+    if rc != 0:
+        raise ValueError("empty or oversized histogram" if rc == -1 else "out of memory")
+    return prob, alias
+
+
+def alias_cell(prob: np.ndarray, alias: np.ndarray, total: int, words) -> int:
+    """Cell drawn by the alias method from one Philox block (4 words)."""
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    return int(lib().oracle_alias_cell(prob.ctypes.data, alias.ctypes.data, prob.size,
+                                       int(total), w.ctypes.data))
 
 
 def cdf_t(w: int, total: int) -> int:

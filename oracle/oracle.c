@@ -12,7 +12,11 @@
  * open:
  *   - sampler: exact inverse CDF over integer cumulative counts of the
  *     flattened 2D histogram (loss index major); one Philox4x32-10 block per
- *     material step gives the cell word and three jitter/azimuth words;
+ *     material step gives the cell word and three jitter/azimuth words.
+ *     Alternatively the alias method of Section "The Alias Method" (Walker's
+ *     Prob/Alias tables, built exactly in integers), which takes its column
+ *     from the cell word and its threshold from the low bytes of the other
+ *     three words;
  *   - jitter: uniform within the drawn cell on both axes (Section
  *     "Simulation", item 2);
  *   - kick: dp_local = |p| (tau cos phi, tau sin phi, -f), rotated into the
@@ -69,6 +73,7 @@ typedef struct {
     double p_min;
     uint64_t seed;
     const double *scales;           /* [n_variants][n_mag] or NULL (all 1) */
+    int32_t sampler;                /* 0 inverse CDF, 1 alias method */
 } orc_problem;
 
 /* ---------------------------------------------------------------------- */
@@ -134,6 +139,71 @@ int64_t oracle_cdf_cell(const uint32_t *cdf, int64_t K, uint32_t t)
         if (cdf[mid] > t) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Alias method (Section "The Alias Method"; Walker 1977).  The K cells are */
+/* recast as K equally likely columns; column c keeps its own cell with    */
+/* probability prob[c] / T and otherwise yields cell alias[c].             */
+/*                                                                        */
+/* Built exactly in integers: every column has capacity T (the histogram  */
+/* total) and starts with weight w_c = K * count_c, so the weights sum to  */
+/* K * T.  Two LIFO worklists hold the columns below capacity ("small")   */
+/* and at or above it ("large"), each filled in ascending cell order.     */
+/* Until "small" is empty: take the top small column s and the top large   */
+/* column l; s keeps prob[s] = w_s and aliases l; l gives up T - w_s of    */
+/* its weight and, once below capacity, moves from "large" to "small".     */
+/* Columns left in "large" then hold exactly T: prob = T, alias = self.    */
+/* ---------------------------------------------------------------------- */
+/* Returns 0, -1 for a zero or oversized total, -2 when out of memory. */
+int oracle_alias_build(const uint32_t *counts, int64_t K, uint32_t *prob, int32_t *alias)
+{
+    uint64_t T = 0;
+    for (int64_t c = 0; c < K; ++c) T += counts[c];
+    if (T == 0 || T > 0xFFFFFFFFull) return -1;
+    uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)K);
+    int64_t *small = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    int64_t *large = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+    if (!w || !small || !large) { free(w); free(small); free(large); return -2; }
+    int64_t ns = 0, nl = 0;
+    for (int64_t c = 0; c < K; ++c) {
+        w[c] = (uint64_t)K * counts[c];
+        if (w[c] < T) small[ns++] = c; else large[nl++] = c;
+    }
+    while (ns > 0 && nl > 0) {
+        int64_t sc = small[--ns];
+        int64_t lc = large[nl - 1];
+        prob[sc] = (uint32_t)w[sc];
+        alias[sc] = (int32_t)lc;
+        w[lc] -= T - w[sc];
+        if (w[lc] < T) {
+            --nl;
+            small[ns++] = lc;
+        }
+    }
+    /* exact arithmetic leaves "small" empty and every remaining large column
+     * at exactly T */
+    while (nl > 0) {
+        int64_t lc = large[--nl];
+        prob[lc] = (uint32_t)T;
+        alias[lc] = (int32_t)lc;
+    }
+    int bad = ns != 0;
+    free(w); free(small); free(large);
+    return bad ? -1 : 0;
+}
+
+/* Column j = floor(w0 * K / 2^32).  Threshold t = floor(x * T / 2^24) with
+ * x the 24-bit word made of the low bytes of w1, w2, w3 (bits the jitter and
+ * azimuth do not use).  The cell is j when t < prob[j], else alias[j]. */
+int64_t oracle_alias_cell(const uint32_t *prob, const int32_t *alias, int64_t K, uint32_t total,
+                          const uint32_t w[4])
+{
+    int64_t j = (int64_t)(((uint64_t)w[0] * (uint64_t)K) >> 32);
+    uint64_t x = (uint64_t)(w[1] & 0xFFu) | ((uint64_t)(w[2] & 0xFFu) << 8) |
+                 ((uint64_t)(w[3] & 0xFFu) << 16);
+    uint64_t t = (x * (uint64_t)total) >> 24;
+    return t < prob[j] ? j : (int64_t)alias[j];
 }
 
 /* ---------------------------------------------------------------------- */
@@ -323,7 +393,14 @@ typedef struct {
     double *step_margin;            /* [n][trace_steps + 1][2] (pos, p) per step, or NULL */
 } orc_out;
 
-static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
+/* Sampling tables of every histogram h = material * n_pbin + bin. */
+typedef struct {
+    uint32_t *cdf;                  /* [n_hist][K] inclusive cumulative counts */
+    uint32_t *prob;                 /* [n_hist][K] alias thresholds (alias method only) */
+    int32_t *alias;                 /* [n_hist][K] alias cells (alias method only) */
+} orc_tables;
+
+static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *in,
                     const orc_out *out, int64_t j)
 {
     double r[3] = {in->x[j], in->y[j], in->z[j]};
@@ -381,9 +458,14 @@ static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
             uint32_t ctr[4] = {(uint32_t)mu, (uint32_t)((uint64_t)mu >> 32), (uint32_t)k, 0u};
             uint32_t w[4];
             oracle_philox(ctr, key, w);
-            const uint32_t *C = cdf + ((int64_t)mat * P->n_pbin + ibin) * K;
-            uint32_t t = oracle_cdf_t(w[0], C[K - 1]);
-            cell = oracle_cdf_cell(C, K, t);
+            const int64_t h = (int64_t)mat * P->n_pbin + ibin;
+            const uint32_t *C = tab->cdf + h * K;
+            if (P->sampler == 1) {
+                cell = oracle_alias_cell(tab->prob + h * K, tab->alias + h * K, K, C[K - 1], w);
+            } else {
+                uint32_t t = oracle_cdf_t(w[0], C[K - 1]);
+                cell = oracle_cdf_cell(C, K, t);
+            }
             int64_t il = cell / P->n_scat, is = cell % P->n_scat;
             double f = P->loss_lo + ((double)il + orc_unit(w[1])) * wl;
             double tau = P->scat_lo + ((double)is + orc_unit(w[2])) * ws;
@@ -424,24 +506,36 @@ static void orc_one(const orc_problem *P, const uint32_t *cdf, const orc_in *in,
 }
 
 /* Propagate n muons.  Returns 0, or -1 for an empty/oversized histogram, or
- * -2 when memory for the cumulative tables cannot be allocated.  Uses
+ * -2 when memory for the sampling tables cannot be allocated.  Uses
  * n_threads OpenMP threads (<= 0: the OpenMP default). */
 int oracle_propagate(const orc_problem *P, int64_t n, const orc_in *in, const orc_out *out,
                      int32_t n_threads)
 {
     const int64_t K = (int64_t)P->n_loss * P->n_scat;
     const int64_t n_hist = (int64_t)P->n_mat * P->n_pbin;
-    uint32_t *cdf = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(K * n_hist > 0 ? K * n_hist : 1));
-    if (!cdf) return -2;
-    for (int64_t h = 0; h < n_hist; ++h)
-        if (oracle_cdf_build(P->counts + h * K, K, cdf + h * K) != 0) { free(cdf); return -1; }
+    const size_t cells = (size_t)(K * n_hist > 0 ? K * n_hist : 1);
+    orc_tables tab = {NULL, NULL, NULL};
+    int rc = 0;
+    tab.cdf = (uint32_t *)malloc(sizeof(uint32_t) * cells);
+    if (P->sampler == 1) {
+        tab.prob = (uint32_t *)malloc(sizeof(uint32_t) * cells);
+        tab.alias = (int32_t *)malloc(sizeof(int32_t) * cells);
+    }
+    if (!tab.cdf || (P->sampler == 1 && (!tab.prob || !tab.alias))) rc = -2;
+    for (int64_t h = 0; h < n_hist && rc == 0; ++h) {
+        if (oracle_cdf_build(P->counts + h * K, K, tab.cdf + h * K) != 0) rc = -1;
+        else if (P->sampler == 1)
+            rc = oracle_alias_build(P->counts + h * K, K, tab.prob + h * K, tab.alias + h * K);
+    }
+    if (rc == 0) {
 #ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
+        if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 64)
 #endif
-    for (int64_t j = 0; j < n; ++j) orc_one(P, cdf, in, out, j);
-    free(cdf);
-    return 0;
+        for (int64_t j = 0; j < n; ++j) orc_one(P, &tab, in, out, j);
+    }
+    free(tab.cdf); free(tab.prob); free(tab.alias);
+    return rc;
 }
 
 int oracle_max_threads(void)

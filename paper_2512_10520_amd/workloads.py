@@ -354,6 +354,7 @@ class RunParams:
     seed: int                    # Philox key
     n_variants: int = 1
     scales: Optional[np.ndarray] = None   # float32 [n_variants][n_mag] or None (= 1)
+    sampler: int = 0             # 0 inverse CDF, 1 alias method
 
 
 @dataclass

@@ -36,7 +36,7 @@ def muons(x, y, z, px, py, pz, q):
 
 
 def workload(hist, geom, mu, step=0.02, max_steps=1000, p_min=0.5, seed=0, field=None,
-             scales=None, n_variants=1):
+             scales=None, n_variants=1, sampler=0):
     return W.Workload("custom", hist, geom, field, mu,
                       W.RunParams(step=step, max_steps=max_steps, p_min=p_min, seed=seed,
-                                  n_variants=n_variants, scales=scales))
+                                  n_variants=n_variants, scales=scales, sampler=sampler))

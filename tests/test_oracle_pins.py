@@ -143,6 +143,92 @@ def test_empty_histogram_rejected():
         oracle.cdf_cells(np.zeros(10, np.uint32), [0])
 
 
+# ------------------------------------------------------- alias method tables
+def _alias_hits(prob, alias, T):
+    """Over every (column, threshold t in [0, T)) pair, how often each cell is
+    the outcome: column j gives its own cell for t < prob[j] and alias[j]
+    for the remaining T - prob[j] thresholds."""
+    K = prob.size
+    hits = np.zeros(K, np.int64)
+    np.add.at(hits, np.arange(K), prob.astype(np.int64))
+    np.add.at(hits, alias.astype(np.int64), T - prob.astype(np.int64))
+    return hits
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_alias_tables_exact(seed):
+    """Walker's construction in integers: every cell is the outcome of exactly
+    K * count of the K * T equally likely (column, threshold) pairs, and an
+    empty cell is never an outcome."""
+    rng = np.random.default_rng(seed)
+    K = int(rng.integers(1, 300))
+    counts = rng.integers(0, 1000, size=K).astype(np.uint32)
+    counts[rng.random(K) < 0.4] = 0
+    counts[int(rng.integers(K))] += 1
+    T = int(counts.sum())
+    prob, alias = oracle.alias_tables(counts)
+    assert np.all(prob <= T) and np.all((alias >= 0) & (alias < K))
+    assert np.array_equal(_alias_hits(prob, alias, T), K * counts.astype(np.int64))
+    empty = counts == 0
+    assert np.all(prob[empty] == 0)
+    assert not np.any(empty[alias[prob < T]])       # only reachable columns alias to a cell
+
+
+def test_alias_tables_special_cases():
+    # equal counts: every column keeps its own cell
+    prob, alias = oracle.alias_tables(np.full(10, 7, np.uint32))
+    assert np.all(prob == 70) and np.array_equal(alias, np.arange(10))
+    # one non-empty cell: every column yields it
+    c = np.zeros(13, np.uint32)
+    c[4] = 5
+    prob, alias = oracle.alias_tables(c)
+    assert np.array_equal(_alias_hits(prob, alias, 5), 13 * c.astype(np.int64))
+    assert np.all(np.where(prob < 5, alias == 4, True))
+    # a single cell, and a total just below 2^32 (weights need 64 bits)
+    prob, alias = oracle.alias_tables(np.array([3], np.uint32))
+    assert prob[0] == 3 and alias[0] == 0
+    c = np.array([2 ** 31, 2 ** 31 - 2, 1], np.uint32)
+    prob, alias = oracle.alias_tables(c)
+    assert np.array_equal(_alias_hits(prob, alias, 2 ** 32 - 1), 3 * c.astype(np.int64))
+    # the largest table the library accepts
+    rng = np.random.default_rng(5)
+    c = rng.integers(0, 60_000, size=65_536).astype(np.uint32)
+    prob, alias = oracle.alias_tables(c)
+    assert np.array_equal(_alias_hits(prob, alias, int(c.sum())), 65_536 * c.astype(np.int64))
+    with pytest.raises(ValueError):
+        oracle.alias_tables(np.zeros(4, np.uint32))
+
+
+def test_alias_draw_column_and_threshold_words():
+    """The column comes from word 0 (floor(w0 K / 2^32)), the threshold from
+    the low bytes of words 1-3 (x = b1 | b2 << 8 | b3 << 16, t = floor(x T /
+    2^24)): the first and last word of each column, and the threshold words
+    either side of each column's split, give the expected cells."""
+    rng = np.random.default_rng(3)
+    counts = rng.integers(0, 20, size=11).astype(np.uint32)
+    counts[2] = 0
+    T = int(counts.sum())
+    K = counts.size
+    prob, alias = oracle.alias_tables(counts)
+
+    def words(w0, x):
+        # high bytes of words 1-3 are set to show that only the low bytes count
+        return [w0, 0xABCDEF00 | (x & 0xFF), 0x12345600 | ((x >> 8) & 0xFF),
+                0x9876FF00 | ((x >> 16) & 0xFF)]
+
+    for j in range(K):
+        first = -(-j * 2 ** 32 // K)
+        last = -(-(j + 1) * 2 ** 32 // K) - 1
+        split = -(-int(prob[j]) * 2 ** 24 // T)          # smallest x with t >= prob[j]
+        for w0 in (first, last):
+            if split > 0:
+                assert oracle.alias_cell(prob, alias, T, words(w0, split - 1)) == j
+                assert oracle.alias_cell(prob, alias, T, words(w0, 0)) == j
+            if split < 2 ** 24:
+                assert oracle.alias_cell(prob, alias, T, words(w0, split)) == alias[j]
+                assert oracle.alias_cell(prob, alias, T, words(w0, 2 ** 24 - 1)) == alias[j]
+
+
 # ------------------------------------------------------- P7: rotation
 def test_rotation_maps_z_to_direction_and_is_orthogonal():
     rng = np.random.default_rng(3)

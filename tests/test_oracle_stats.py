@@ -11,6 +11,7 @@ integrals over the histogram cells.
 import math
 
 import numpy as np
+import pytest
 from scipy import stats
 
 import oracle
@@ -18,10 +19,13 @@ from paper_2512_10520_amd import workloads as W
 from tests import _custom as CU
 
 
-def _one_step(hist, n, P=100.0):
+SAMPLERS = pytest.mark.parametrize("sampler", [0, 1], ids=["cdf", "alias"])
+
+
+def _one_step(hist, n, P=100.0, sampler=0):
     geom = CU.geometry([[-10, 10, -10, 10, 0, 100]], [0])
     mu = CU.muons(np.zeros(n), 0.0, 0.01, 0.0, 0.0, P, 1)
-    wl = CU.workload(hist, geom, mu, max_steps=1, p_min=0.1)
+    wl = CU.workload(hist, geom, mu, max_steps=1, p_min=0.1, sampler=sampler)
     res = oracle.propagate(wl)
     assert np.all(res.n_steps == 1)
     px, py, pz = res.state[3:]
@@ -47,10 +51,11 @@ def _chi2_p(obs, expected):
     return stats.chisquare(o, e * o.sum() / e.sum()).pvalue
 
 
-def test_sampled_cells_and_marginals_match_histogram():
+@SAMPLERS
+def test_sampled_cells_and_marginals_match_histogram(sampler):
     hist = CU.flat_histograms(n_pbin=4, n_loss=8, n_scat=8, seed=21)
     n = 1_000_000
-    f, tau, phi = _one_step(hist, n)
+    f, tau, phi = _one_step(hist, n, sampler=sampler)
     il, is_, fl, fs = _cells(hist, f, tau)
     counts = hist.counts[0, 0].astype(np.float64)
     assert il.min() >= 0 and il.max() < 8 and is_.min() >= 0 and is_.max() < 8
@@ -69,11 +74,12 @@ def test_sampled_cells_and_marginals_match_histogram():
     assert abs(np.corrcoef(fl, phi)[0, 1]) < 5 / math.sqrt(n)
 
 
-def test_sampled_cells_realistic_histogram():
+@SAMPLERS
+def test_sampled_cells_realistic_histogram(sampler):
     wl = W.make_workload("tiny", n_muons=1)
     hist = wl.hist
     n = 500_000
-    f, tau, _ = _one_step(hist, n, P=100.0)              # 100 GeV: momentum bin 24
+    f, tau, _ = _one_step(hist, n, P=100.0, sampler=sampler)   # 100 GeV: momentum bin 24
     il, is_, _, _ = _cells(hist, f, tau)
     counts = hist.counts[0, 24].astype(np.float64).ravel()
     obs = np.bincount(il * hist.n_scat + is_, minlength=counts.size).astype(np.float64)
@@ -104,12 +110,14 @@ def _cell_moments(hist):
     return m1, m2
 
 
-def test_log_momentum_moments_over_many_steps():
+@SAMPLERS
+def test_log_momentum_moments_over_many_steps(sampler):
     hist = CU.flat_histograms(n_pbin=4, n_loss=8, n_scat=8, seed=9, p_lo=1.0, p_hi=1000.0)
     n, N = 100_000, 50
     geom = CU.geometry([[-10, 10, -10, 10, 0, 100]], [0])
     mu = CU.muons(np.zeros(n), 0.0, 0.01, 0.0, 0.0, 100.0, 1)
-    res = oracle.propagate(CU.workload(hist, geom, mu, max_steps=N, p_min=0.1))
+    res = oracle.propagate(CU.workload(hist, geom, mu, max_steps=N, p_min=0.1,
+                                       sampler=sampler))
     assert np.all(res.n_steps == N) and np.all(res.status == oracle.ST_STEPS)
     s = np.log(np.linalg.norm(res.state[3:], axis=0) / 100.0)
     m1, m2 = _cell_moments(hist)
