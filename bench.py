@@ -54,6 +54,9 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="block", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="auto", choices=["auto", "plain", "persistent"])
+    ap.add_argument("--sampler", default="cdf", choices=["cdf", "alias"],
+                    help="histogram-cell sampler of the timed pass (the other one is timed "
+                         "beside it on the block workload)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-design", action="store_true")
     ap.add_argument("--cpu-muons", type=int, default=1_000_000)
@@ -116,8 +119,9 @@ def main():
         scales = torch.from_numpy(np.ascontiguousarray(wl.run.scales, np.float32)).cuda()
     use_graph = args.config == "scan"
 
-    def spec_for(mode):
-        return api.RunSpec.from_workload(wl, mode=mode, use_graph=use_graph and mode == "persistent")
+    def spec_for(mode, sampler=args.sampler):
+        return api.RunSpec.from_workload(wl, mode=mode, sampler=sampler,
+                                         use_graph=use_graph and mode == "persistent")
 
     modes = ["plain", "persistent"] if args.mode == "auto" else [args.mode]
     if "persistent" in modes:
@@ -155,11 +159,26 @@ def main():
             "data": "synthetic",
             "config": {"workload": WORKLOADS[args.config], "muons": len(dm),
                        "lanes": int(out.n_steps.numel()), "muon_steps_per_pass": steps_per_pass,
-                       "mode": mode, "mode_probe_ms": probe, "autotune": tuned},
+                       "mode": mode, "sampler": args.sampler, "mode_probe_ms": probe,
+                       "autotune": tuned},
             "roofline": roofline}
 
     if args.config == "scan":
         line["config"]["per_variant_plain_ms"] = per_variant_plain(api, dm, wl, scales, torch)
+
+    if args.config in ("block", "shield"):
+        other = "alias" if args.sampler == "cdf" else "cdf"
+        so = spec_for(mode, other)
+        oo = api.alloc_result(so, len(dm), "cuda")
+        for _ in range(max(1, args.warmup)):
+            api.propagate(dm, so, scales=scales, out=oo)
+        torch.cuda.synchronize()
+        st = int(oo.n_steps.to(torch.int64).sum().item())
+        _, oms = _time_launches(lambda: api.propagate(dm, so, scales=scales, out=oo),
+                                max(2, min(args.steps, 5)), torch)
+        line["other_sampler"] = {"sampler": other, "mode": mode, "kernel_ms": oms,
+                                 "muon_steps_per_pass": st,
+                                 "muon_steps_per_s": st / (oms * 1e-3)}
 
     if not args.no_design and args.config == "block":
         line["design_step"] = design_step(api, W, torch)

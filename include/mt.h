@@ -62,6 +62,14 @@ extern "C" {
 #define MT_MODE_PLAIN       0    /* one lane per muon until it stops */
 #define MT_MODE_PERSISTENT  1    /* resident grid, atomic work queue, compaction */
 
+/* ---- samplers of the histogram cell ------------------------------------ */
+#define MT_SAMPLER_CDF      0    /* exact inverse CDF over integer counts */
+#define MT_SAMPLER_ALIAS    1    /* Walker alias method (Section "The Alias Method") */
+
+/* ---- field map lookup and field evaluation ------------------------------ */
+#define MT_INTERP_TRILINEAR 0    /* trilinear interpolation of the map */
+#define MT_INTERP_NEAREST   1    /* value of the nearest node (Section "Simulation", item 3) */
+
 /* Documented table limits. */
 #define MT_MAX_BOXES      64     /* boxes in the geometry */
 #define MT_MAX_PBINS      1024   /* momentum bins */
@@ -80,6 +88,9 @@ extern "C" {
  *            e_P use bin P-1 (no interpolation between bins).
  *   counts   host uint32 [n_mat][n_pbin][n_loss][n_scat] (loss index major);
  *            each histogram's total must lie in [1, 2^32).
+ * Both samplers' tables are built: inclusive cumulative counts (with a guide
+ * table) for MT_SAMPLER_CDF and Walker Prob/Alias tables for
+ * MT_SAMPLER_ALIAS (Section "The Alias Method"), exact in integers.
  * Limits: n_pbin <= MT_MAX_PBINS, n_mat * n_pbin <= MT_MAX_HISTS,
  * n_loss * n_scat <= MT_MAX_CELLS.
  * Errors: MT_ERR_INVALID_ARG, MT_ERR_EMPTY_HIST, MT_ERR_LIMIT, MT_ERR_OOM,
@@ -141,6 +152,13 @@ typedef struct mt_result {
  * slot g of the outputs.  All variants of muon j draw the same random numbers
  * (common random numbers): the Philox4x32-10 key is the 64-bit seed and the
  * counter is (j mod 2^32, j / 2^32, step, 0).  Vacuum steps draw nothing.
+ * A material step turns the four output words w0..w3 into a cell and a
+ * point in it: the cell from w0 (MT_SAMPLER_CDF: t = floor(w0 T / 2^32),
+ * first cell whose cumulative count exceeds t; MT_SAMPLER_ALIAS: column
+ * floor(w0 K / 2^32), kept when floor(x T / 2^24) is below its threshold,
+ * else its alias, with x = the low bytes of w1, w2, w3 as a 24-bit number),
+ * the jitters inside the cell and the azimuth from the top 24 bits of w1,
+ * w2 and w3.
  */
 typedef struct mt_params {
     double   step_m;          /* fixed step length d (> 0) */
@@ -164,6 +182,11 @@ typedef struct mt_params {
     /* per-variant tallies at a detector plane (design scan) */
     double  *tally;           /* device [n_variants][3] or NULL: see mt_propagate */
     double   z_det, r_ap, r_scale;
+    int32_t  sampler;         /* MT_SAMPLER_CDF (0) or MT_SAMPLER_ALIAS */
+    int32_t  interp;          /* MT_INTERP_TRILINEAR (0) or MT_INTERP_NEAREST */
+    int32_t  stage_field;     /* 0: field fetched once at the step start and held over the
+                                 RK4 stages (Algorithm 1); 1: evaluated at every stage
+                                 position (box lookup + map there) */
 } mt_params;
 
 /*
@@ -190,7 +213,9 @@ int mt_propagate(const mt_params *params, int64_t n, const mt_muons *in, mt_muon
  * extension suggested in Section "Discussion and Conclusion"): sampled
  * losses, kicks, azimuths, materials, bins and step counts are held fixed.
  * Requires the same params, in, res, ckpt and tape as the forward call,
- * which must have used ckpt_every = 16 and MT_MODE_PLAIN.
+ * which must have used ckpt_every = 16 and MT_MODE_PLAIN.  The differentiable
+ * form supports the held trilinear field only: checkpointing with
+ * MT_INTERP_NEAREST or stage_field = 1 is rejected (MT_ERR_INVALID_ARG).
  *
  *   g_out     device double [6][lanes]: dL/d(final x, y, z, px, py, pz)
  *   g_in      device double [6][lanes]: receives dL/d(initial state)

@@ -47,7 +47,9 @@ class _Problem(C.Structure):
         ("scat_lo", C.c_double), ("scat_hi", C.c_double),
         ("counts", C.c_void_p),
         ("n_box", C.c_int32),
-        ("box", C.c_void_p), ("material", C.c_void_p), ("b_box", C.c_void_p),
+        ("box", C.c_void_p),
+        ("n_poly", C.c_int32), ("poly", C.c_void_p),
+        ("material", C.c_void_p), ("b_box", C.c_void_p),
         ("magnet", C.c_void_p),
         ("n_mag", C.c_int32),
         ("world", C.c_double * 3),
@@ -58,6 +60,8 @@ class _Problem(C.Structure):
         ("seed", C.c_uint64),
         ("scales", C.c_void_p),
         ("sampler", C.c_int32),
+        ("interp", C.c_int32),
+        ("stage_field", C.c_int32),
     ]
 
 
@@ -95,9 +99,12 @@ def lib():
             L.oracle_rk4.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p]
             L.oracle_lookup.argtypes = [C.POINTER(_Problem), C.c_void_p]
             L.oracle_lookup.restype = C.c_int32
+            L.oracle_poly_inside.argtypes = [C.c_void_p, C.c_void_p]
+            L.oracle_poly_inside.restype = C.c_int32
             L.oracle_pbin.argtypes = [C.POINTER(_Problem), C.c_double]
             L.oracle_pbin.restype = C.c_int32
             L.oracle_trilinear.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p]
+            L.oracle_nearest.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p]
             L.oracle_propagate.argtypes = [C.POINTER(_Problem), C.c_int64, C.POINTER(_In),
                                            C.POINTER(_Out), C.c_int32]
             L.oracle_propagate.restype = C.c_int
@@ -127,8 +134,15 @@ class Problem:
         P.p_edges = _ptr(keep(h.p_edges, np.float64))
         P.loss_lo, P.loss_hi, P.scat_lo, P.scat_hi = h.loss_lo, h.loss_hi, h.scat_lo, h.scat_hi
         P.counts = _ptr(keep(h.counts, np.uint32))
-        P.n_box = len(g.material)
-        P.box = _ptr(keep(g.box, np.float64))
+        poly = getattr(g, "poly", None)
+        if poly is not None:
+            P.n_box, P.box = 0, None
+            P.n_poly = len(g.material)
+            P.poly = _ptr(keep(np.asarray(poly).reshape(-1, 18), np.float64))
+        else:
+            P.n_box = len(g.material)
+            P.box = _ptr(keep(g.box, np.float64))
+            P.n_poly, P.poly = 0, None
         P.material = _ptr(keep(g.material, np.int32))
         P.b_box = _ptr(keep(g.b_box, np.float32))
         P.magnet = _ptr(keep(g.magnet, np.int32))
@@ -148,6 +162,8 @@ class Problem:
         sc = r.scales if scales is None else scales
         P.scales = None if sc is None else _ptr(keep(sc, np.float64))
         P.sampler = int(getattr(r, "sampler", 0))
+        P.interp = int(getattr(r, "interp", 0))
+        P.stage_field = int(getattr(r, "stage_field", 0))
         self.struct = P
 
 
@@ -275,6 +291,13 @@ def lookup(wl, r) -> int:
     return int(lib().oracle_lookup(C.byref(prob.struct), r.ctypes.data))
 
 
+def poly_inside(block, r) -> bool:
+    """Is r inside one block (float64 [18]: z_lo, z_hi, bottom quad, top quad)?"""
+    b = np.ascontiguousarray(block, dtype=np.float64).ravel()
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    return bool(lib().oracle_poly_inside(b.ctypes.data, r.ctypes.data))
+
+
 def pbin(wl, pm: float) -> int:
     prob = Problem(wl)
     return int(lib().oracle_pbin(C.byref(prob.struct), float(pm)))
@@ -285,6 +308,14 @@ def trilinear(wl, r) -> np.ndarray:
     r = np.ascontiguousarray(r, dtype=np.float64)
     o = np.zeros(3)
     lib().oracle_trilinear(C.byref(prob.struct), r.ctypes.data, o.ctypes.data)
+    return o
+
+
+def nearest(wl, r) -> np.ndarray:
+    prob = Problem(wl)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    o = np.zeros(3)
+    lib().oracle_nearest(C.byref(prob.struct), r.ctypes.data, o.ctypes.data)
     return o
 
 

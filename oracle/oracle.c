@@ -25,7 +25,10 @@
  *   - field: per-box uniform field times the magnet's scale plus a trilinear
  *     interpolation of a node-centred map (zero outside it), evaluated once at
  *     the start of the step and held fixed through the RK4 stages (Algorithm
- *     1 fetches B once before RK4Step);
+ *     1 fetches B once before RK4Step).  Options: the map read by
+ *     nearest-neighbour lookup (the retrieval Section "Simulation", item 3
+ *     names), and the field evaluated afresh at every RK4 stage position
+ *     (the textbook RK4 of a position-dependent force);
  *   - equation of motion: the Lorentz force of Eq. (3) with E = 0 written in
  *     arc length s: dr/ds = p/|p|, dp/ds = kappa q (p/|p|) x B with
  *     kappa = 0.299792458 GeV/(c T m), integrated with classical RK4 over the
@@ -33,7 +36,13 @@
  *   - break test: |p| < p_min, z >= z_max, |x| >= x_max, |y| >= y_max, in
  *     that order, at the top of each iteration; the step cap ends the loop;
  *   - containment: half-open boxes, lowest index wins; momentum bin i with
- *     e_i <= |p| < e_{i+1}, clamped to [0, P-1].
+ *     e_i <= |p| < e_{i+1}, clamped to [0, P-1].  Alternatively the geometry
+ *     is a list of convex blocks (Section "Simulation", item 1): each has a
+ *     z range [z_lo, z_hi) and a quadrilateral at either end; the slice at
+ *     height z interpolates the two linearly and a point is inside when the
+ *     edge cross products S_i of Eq. (1) (the sign test) are all >= 0 or all
+ *     <= 0; lowest index wins.  The oracle tests every block (the spatial
+ *     hashing grid of the paper only prunes candidates).
  *
  * Parity pins for every function here live in tests/test_oracle_*.py.
  */
@@ -58,6 +67,9 @@ typedef struct {
     /* geometry */
     int32_t n_box;
     const double *box;              /* [n_box][6] xlo xhi ylo yhi zlo zhi */
+    int32_t n_poly;                 /* > 0: the volumes are these blocks, not boxes */
+    const double *poly;             /* [n_poly][18] z_lo, z_hi, quad at z_lo (x0 y0 .. x3 y3),
+                                       quad at z_hi (same vertex order) */
     const int32_t *material;        /* [n_box], -1 vacuum */
     const float *b_box;             /* [n_box][3] tesla, or NULL */
     const int32_t *magnet;          /* [n_box], -1 unscaled, or NULL */
@@ -74,6 +86,8 @@ typedef struct {
     uint64_t seed;
     const double *scales;           /* [n_variants][n_mag] or NULL (all 1) */
     int32_t sampler;                /* 0 inverse CDF, 1 alias method */
+    int32_t interp;                 /* map lookup: 0 trilinear, 1 nearest node */
+    int32_t stage_field;            /* 0 B held from the step start, 1 B at every stage */
 } orc_problem;
 
 /* ---------------------------------------------------------------------- */
@@ -273,8 +287,48 @@ void oracle_rk4(const double y_in[6], double q, const double B[3], double h, dou
 /* ---------------------------------------------------------------------- */
 /* Geometry: lowest-index half-open box containing r, or -1.              */
 /* ---------------------------------------------------------------------- */
+/* Slice of block b at height z: vertex i = (1 - t) bottom_i + t top_i with
+ * t = (z - z_lo) / (z_hi - z_lo). */
+static void orc_poly_slice(const double *pb, double z, double v[4][2])
+{
+    double t = (z - pb[0]) / (pb[1] - pb[0]);
+    for (int i = 0; i < 4; ++i) {
+        v[i][0] = (1.0 - t) * pb[2 + 2 * i] + t * pb[10 + 2 * i];
+        v[i][1] = (1.0 - t) * pb[3 + 2 * i] + t * pb[11 + 2 * i];
+    }
+}
+
+/* Eq. (1): S_i = e_ix (p_y - v_iy) - e_iy (p_x - v_ix), e_i = v_{i+1} - v_i. */
+static void orc_poly_signs(const double v[4][2], const double r[3], double S[4])
+{
+    for (int i = 0; i < 4; ++i) {
+        const double *a = v[i], *b = v[(i + 1) % 4];
+        double ex = b[0] - a[0], ey = b[1] - a[1];
+        S[i] = ex * (r[1] - a[1]) - ey * (r[0] - a[0]);
+    }
+}
+
+int32_t oracle_poly_inside(const double *pb, const double r[3])
+{
+    if (!(pb[0] <= r[2] && r[2] < pb[1])) return 0;
+    double v[4][2], S[4];
+    orc_poly_slice(pb, r[2], v);
+    orc_poly_signs(v, r, S);
+    int pos = 1, neg = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (S[i] < 0.0) pos = 0;
+        if (S[i] > 0.0) neg = 0;
+    }
+    return pos || neg;
+}
+
 int32_t oracle_lookup(const orc_problem *P, const double r[3])
 {
+    if (P->n_poly > 0) {
+        for (int32_t b = 0; b < P->n_poly; ++b)
+            if (oracle_poly_inside(P->poly + 18 * b, r)) return b;
+        return -1;
+    }
     for (int32_t b = 0; b < P->n_box; ++b) {
         const double *bx = P->box + 6 * b;
         if (bx[0] <= r[0] && r[0] < bx[1] &&
@@ -290,6 +344,26 @@ int32_t oracle_lookup(const orc_problem *P, const double r[3])
 static double orc_geom_margin(const orc_problem *P, const double r[3])
 {
     double m = INFINITY;
+    if (P->n_poly > 0) {
+        /* distance to the z faces and, inside the z range, the in-slice
+         * distance |S_i| / |e_i| to each edge line */
+        for (int32_t b = 0; b < P->n_poly; ++b) {
+            const double *pb = P->poly + 18 * b;
+            double d = fabs(r[2] - pb[0]);
+            if (fabs(pb[1] - r[2]) < d) d = fabs(pb[1] - r[2]);
+            if (d < m) m = d;
+            if (!(pb[0] <= r[2] && r[2] < pb[1])) continue;
+            double v[4][2], S[4];
+            orc_poly_slice(pb, r[2], v);
+            orc_poly_signs(v, r, S);
+            for (int i = 0; i < 4; ++i) {
+                double ex = v[(i + 1) % 4][0] - v[i][0], ey = v[(i + 1) % 4][1] - v[i][1];
+                double e = sqrt(ex * ex + ey * ey);
+                if (e > 0.0 && fabs(S[i]) / e < m) m = fabs(S[i]) / e;
+            }
+        }
+        return m;
+    }
     for (int32_t b = 0; b < P->n_box; ++b) {
         const double *bx = P->box + 6 * b;
         double inside_margin = INFINITY, outside_violation = 0.0;
@@ -356,10 +430,62 @@ void oracle_trilinear(const orc_problem *P, const double r[3], double B[3])
             }
 }
 
+/* Nearest-neighbour lookup: the value of the node closest to r on every axis
+ * (a point half-way between two nodes takes the higher one), zero outside
+ * [lo, hi] as for the trilinear form. */
+void oracle_nearest(const orc_problem *P, const double r[3], double B[3])
+{
+    B[0] = B[1] = B[2] = 0.0;
+    if (P->nx <= 0 || P->map == NULL) return;
+    const int32_t n[3] = {P->nx, P->ny, P->nz};
+    int32_t i[3];
+    for (int a = 0; a < 3; ++a) {
+        if (r[a] < P->map_lo[a] || r[a] > P->map_hi[a]) return;
+        double u = (r[a] - P->map_lo[a]) / (P->map_hi[a] - P->map_lo[a]) * (double)(n[a] - 1);
+        int32_t k = (int32_t)floor(u + 0.5);
+        if (k > n[a] - 1) k = n[a] - 1;
+        i[a] = k;
+    }
+    int64_t node = ((int64_t)i[2] * n[1] + i[1]) * n[0] + i[0];
+    const float *b = P->map + 3 * node;
+    B[0] = (double)b[0];
+    B[1] = (double)b[1];
+    B[2] = (double)b[2];
+}
+
+/* Decision margin of the map lookup at r: distance to the faces of the
+ * map's domain (the field drops to zero outside it) and, for the nearest-
+ * node lookup, to the mid-planes between nodes. */
+static double orc_map_margin(const orc_problem *P, const double r[3])
+{
+    double m = INFINITY;
+    if (P->nx <= 0 || P->map == NULL) return m;
+    const int32_t n[3] = {P->nx, P->ny, P->nz};
+    for (int a = 0; a < 3; ++a) {
+        double d = fabs(r[a] - P->map_lo[a]);
+        if (fabs(P->map_hi[a] - r[a]) < d) d = fabs(P->map_hi[a] - r[a]);
+        if (d < m) m = d;
+        if (P->interp == 1 && r[a] >= P->map_lo[a] && r[a] <= P->map_hi[a]) {
+            double sp = (P->map_hi[a] - P->map_lo[a]) / (double)(n[a] - 1);
+            double u = (r[a] - P->map_lo[a]) / sp;
+            double f = u - floor(u);              /* mid-plane at f = 0.5 */
+            d = fabs(f - 0.5) * sp;
+            if (d < m) m = d;
+        }
+    }
+    return m;
+}
+
+static void orc_map(const orc_problem *P, const double r[3], double B[3])
+{
+    if (P->interp == 1) oracle_nearest(P, r, B);
+    else oracle_trilinear(P, r, B);
+}
+
 static void orc_field(const orc_problem *P, int32_t vol, int32_t variant, const double r[3],
                       double B[3])
 {
-    oracle_trilinear(P, r, B);
+    orc_map(P, r, B);
     if (vol >= 0 && P->b_box != NULL) {
         double s = 1.0;
         if (P->magnet != NULL && P->magnet[vol] >= 0 && P->scales != NULL)
@@ -368,6 +494,32 @@ static void orc_field(const orc_problem *P, int32_t vol, int32_t variant, const 
         B[1] += s * (double)P->b_box[3 * vol + 1];
         B[2] += s * (double)P->b_box[3 * vol + 2];
     }
+}
+
+/* RK4 step with the field evaluated at every stage position: the field
+ * there is the scaled field of the box containing that point plus the map.
+ * *margin receives the smallest decision margin (box faces, map) over the
+ * three stage points after the first. */
+static void orc_rk4_stages(const orc_problem *P, int32_t variant, const double y_in[6], double q,
+                           double h, double y_out[6], double *margin)
+{
+    double k1[6], k2[6], k3[6], k4[6], t[6], B[3], d;
+    orc_field(P, oracle_lookup(P, y_in), variant, y_in, B);
+    orc_deriv(y_in, q, B, k1);
+    double *ks[3] = {k2, k3, k4};
+    const double *prev[3] = {k1, k2, k3};
+    const double c[3] = {0.5 * h, 0.5 * h, h};
+    for (int s = 0; s < 3; ++s) {
+        for (int a = 0; a < 6; ++a) t[a] = y_in[a] + c[s] * prev[s][a];
+        d = orc_geom_margin(P, t);
+        if (d < *margin) *margin = d;
+        d = orc_map_margin(P, t);
+        if (d < *margin) *margin = d;
+        orc_field(P, oracle_lookup(P, t), variant, t, B);
+        orc_deriv(t, q, B, ks[s]);
+    }
+    for (int a = 0; a < 6; ++a)
+        y_out[a] = y_in[a] + h / 6.0 * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -483,10 +635,20 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
             int32_t *tr = out->trace + ((int64_t)j * out->trace_steps + k) * 3;
             tr[0] = vol; tr[1] = ibin; tr[2] = (int32_t)cell;
         }
-        double B[3];
-        orc_field(P, vol, var, r, B);
+        d = orc_map_margin(P, r);
+        if (d < mpos) mpos = d;
+        if (sm && d < sm[0]) sm[0] = d;
         double y[6] = {r[0], r[1], r[2], p[0], p[1], p[2]}, yn[6];
-        oracle_rk4(y, q, B, P->step, yn);
+        if (P->stage_field) {
+            double ms = INFINITY;
+            orc_rk4_stages(P, var, y, q, P->step, yn, &ms);
+            if (ms < mpos) mpos = ms;
+            if (sm && ms < sm[0]) sm[0] = ms;
+        } else {
+            double B[3];
+            orc_field(P, vol, var, r, B);
+            oracle_rk4(y, q, B, P->step, yn);
+        }
         r[0] = yn[0]; r[1] = yn[1]; r[2] = yn[2];
         p[0] = yn[3]; p[1] = yn[4]; p[2] = yn[5];
         ++k;

@@ -17,6 +17,8 @@ MT_OK = 0
 ERRORS = {-1: "MT_ERR_INVALID_ARG", -2: "MT_ERR_SHAPE", -3: "MT_ERR_EMPTY_HIST",
           -4: "MT_ERR_NOT_LOADED", -5: "MT_ERR_OOM", -6: "MT_ERR_HIP", -7: "MT_ERR_LIMIT"}
 MT_MODE_PLAIN, MT_MODE_PERSISTENT = 0, 1
+MT_SAMPLER_CDF, MT_SAMPLER_ALIAS = 0, 1
+MT_INTERP_TRILINEAR, MT_INTERP_NEAREST = 0, 1
 ST_RUNNING, ST_PMIN, ST_ZMAX, ST_XMAX, ST_YMAX, ST_MAXSTEPS, ST_INVALID = range(7)
 CKPT_EVERY = 16
 
@@ -35,6 +37,7 @@ class MtParams(C.Structure):
         ("tape", C.c_void_p), ("trace", C.c_void_p), ("n_trace", C.c_int64),
         ("trace_steps", C.c_int32), ("tally", C.c_void_p),
         ("z_det", C.c_double), ("r_ap", C.c_double), ("r_scale", C.c_double),
+        ("sampler", C.c_int32), ("interp", C.c_int32), ("stage_field", C.c_int32),
     ]
 
 

@@ -15,6 +15,10 @@ from . import _lib
 from ._lib import MtMuons, MtParams, MtResult, check
 
 MODES = {"plain": _lib.MT_MODE_PLAIN, "persistent": _lib.MT_MODE_PERSISTENT}
+SAMPLERS = {"cdf": _lib.MT_SAMPLER_CDF, "alias": _lib.MT_SAMPLER_ALIAS}
+SAMPLER_NAMES = {v: k for k, v in SAMPLERS.items()}
+INTERPS = {"trilinear": _lib.MT_INTERP_TRILINEAR, "nearest": _lib.MT_INTERP_NEAREST}
+INTERP_NAMES = {v: k for k, v in INTERPS.items()}
 
 
 def _host(a, dtype) -> np.ndarray:
@@ -142,10 +146,16 @@ class RunSpec:
     block: int = 0
     compact_every: int = 0
     use_graph: bool = False
+    sampler: str = "cdf"           # "cdf" (inverse CDF) or "alias"
+    interp: str = "trilinear"      # field map lookup: "trilinear" or "nearest"
+    stage_field: bool = False      # evaluate the field at every RK4 stage
 
     @staticmethod
     def from_workload(wl, **kw) -> "RunSpec":
         r = wl.run
+        kw.setdefault("sampler", SAMPLER_NAMES[getattr(r, "sampler", 0)])
+        kw.setdefault("interp", INTERP_NAMES[getattr(r, "interp", 0)])
+        kw.setdefault("stage_field", bool(getattr(r, "stage_field", 0)))
         return RunSpec(step=r.step, max_steps=r.max_steps, p_min=r.p_min, seed=r.seed,
                        n_variants=r.n_variants, **kw)
 
@@ -160,7 +170,8 @@ def _params(spec: RunSpec, scales, ckpt=None, tape=None, trace=None, n_trace=0, 
                     ckpt_every=_lib.CKPT_EVERY if ckpt is not None else 0, ckpt=_ptr(ckpt),
                     tape=_ptr(tape), trace=_ptr(trace), n_trace=int(n_trace),
                     trace_steps=int(trace_steps), tally=_ptr(tally), z_det=float(z_det),
-                    r_ap=float(r_ap), r_scale=float(r_scale))
+                    r_ap=float(r_ap), r_scale=float(r_scale), sampler=SAMPLERS[spec.sampler],
+                    interp=INTERPS[spec.interp], stage_field=int(bool(spec.stage_field)))
 
 
 def _check_scales(scales, spec: RunSpec):

@@ -85,7 +85,7 @@ struct State {
     bool hist_loaded = false, geom_loaded = false;
     int n_mat = 0, n_pbin = 0;
     int64_t version = 0;  // bumped on every table change
-    DevBuf cdf, guide, totals, edges2;
+    DevBuf cdf, guide, totals, edges2, alias;
     DevBuf box4, material, bfield, magnet, slab_z, slab_mask;
     DevBuf map;
     DevBuf queue, partial, scratch, gs_lane, zero_dummy;
@@ -187,6 +187,15 @@ int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *
     if (p->block != 0 && (p->block < 64 || p->block > 1024 || p->block % 64 != 0))
         return fail(MT_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
     if (p->compact_every < 0) return fail(MT_ERR_INVALID_ARG, "compact_every must be >= 0");
+    if (p->sampler != MT_SAMPLER_CDF && p->sampler != MT_SAMPLER_ALIAS)
+        return fail(MT_ERR_INVALID_ARG, "unknown sampler %d", p->sampler);
+    if (p->interp != MT_INTERP_TRILINEAR && p->interp != MT_INTERP_NEAREST)
+        return fail(MT_ERR_INVALID_ARG, "unknown interp %d", p->interp);
+    if (p->stage_field != 0 && p->stage_field != 1)
+        return fail(MT_ERR_INVALID_ARG, "stage_field must be 0 or 1");
+    if (p->ckpt_every != 0 && (p->interp != MT_INTERP_TRILINEAR || p->stage_field != 0))
+        return fail(MT_ERR_INVALID_ARG, "the differentiable form (ckpt_every) supports the "
+                                        "held trilinear field only");
     if (p->ckpt_every != 0 && p->ckpt_every != mt::kCkptEvery)
         return fail(MT_ERR_INVALID_ARG, "ckpt_every must be 0 or %d", mt::kCkptEvery);
     if (p->ckpt_every != 0) {
@@ -225,6 +234,9 @@ int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *
     c.compact = p->compact_every ? p->compact_every : 16;
     mt::DevRun &R = c.R;
     R.h = p->step_m;
+    R.sampler = p->sampler;
+    R.interp = p->interp;
+    R.stage_field = p->stage_field;
     R.pmin2 = p->p_min * p->p_min;
     R.max_steps = p->max_steps;
     R.key0 = (uint32_t)p->seed;
@@ -384,6 +396,41 @@ int propagate_impl(const mt_params *p, int64_t n, const mt_muons *in, mt_muons *
 
 extern "C" {
 
+// Walker alias table of one histogram (the Prob/Alias tables of the paper's
+// alias method), in exact integer arithmetic.  Column c starts with weight
+// K * count[c] against a capacity of T = total; LIFO worklists of the
+// columns under capacity ("under") and at or over it ("over"), each filled
+// in ascending order, are paired off: the top "under" column keeps its
+// weight as its threshold and takes the top "over" column as its alias,
+// which loses the difference to T and moves to "under" once below T.
+// Columns still "over" at the end hold exactly T and alias themselves.
+// Entry c of the result is (x_split, alias): the draw keeps cell c when the
+// 24-bit threshold word x is below x_split = ceil(threshold * 2^24 / T),
+// which is the same as floor(x * T / 2^24) < threshold.
+static void alias_table(const uint32_t *count, int64_t K, uint64_t T, uint2 *out) {
+    std::vector<uint64_t> wt((size_t)K);
+    std::vector<int32_t> under, over;
+    under.reserve((size_t)K);
+    over.reserve((size_t)K);
+    for (int64_t c = 0; c < K; ++c) {
+        wt[(size_t)c] = (uint64_t)K * count[c];
+        (wt[(size_t)c] < T ? under : over).push_back((int32_t)c);
+    }
+    auto split_of = [T](uint64_t thr) { return (uint32_t)(((thr << 24) + T - 1) / T); };
+    while (!under.empty() && !over.empty()) {
+        const int32_t u = under.back();
+        under.pop_back();
+        const int32_t o = over.back();
+        out[u] = make_uint2(split_of(wt[(size_t)u]), (uint32_t)o);
+        wt[(size_t)o] -= T - wt[(size_t)u];
+        if (wt[(size_t)o] < T) {
+            over.pop_back();
+            under.push_back(o);
+        }
+    }
+    for (int32_t o : over) out[o] = make_uint2(1u << 24, (uint32_t)o);
+}
+
 int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int32_t n_loss,
                        double loss_lo, double loss_hi, int32_t n_scat, double scat_lo,
                        double scat_hi, const uint32_t *counts) {
@@ -419,6 +466,7 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
     }
     const int64_t G = (int64_t)1 << gbits;
     std::vector<uint32_t> cdf((size_t)(nh * K)), guide((size_t)(nh * G)), totals((size_t)nh);
+    std::vector<uint2> alias((size_t)(nh * K));
     for (int64_t h = 0; h < nh; ++h) {
         uint64_t acc = 0;
         const uint32_t *src = counts + h * K;
@@ -446,6 +494,7 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
             const uint32_t hi = cell_of((uint32_t)((w_hi * T) >> 32));
             Gd[gi] = lo | (hi << 16);
         }
+        alias_table(src, K, T, alias.data() + h * K);
     }
     std::vector<double> e2((size_t)n_pbin + 1);
     for (int i = 0; i <= n_pbin; ++i) e2[i] = p_edges[i] * p_edges[i];
@@ -454,11 +503,13 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
     if ((rc = g.guide.upload(guide.data(), guide.size() * 4))) return rc;
     if ((rc = g.totals.upload(totals.data(), totals.size() * 4))) return rc;
     if ((rc = g.edges2.upload(e2.data(), e2.size() * 8))) return rc;
+    if ((rc = g.alias.upload(alias.data(), alias.size() * sizeof(uint2)))) return rc;
     mt::DevHist &H = g.T.hist;
     H.cdf = reinterpret_cast<const uint32_t *>(g.cdf.p);
     H.guide = reinterpret_cast<const uint32_t *>(g.guide.p);
     H.totals = reinterpret_cast<const uint32_t *>(g.totals.p);
     H.edges2 = reinterpret_cast<const double *>(g.edges2.p);
+    H.alias = reinterpret_cast<const uint2 *>(g.alias.p);
     H.n_mat = n_mat;
     H.n_pbin = n_pbin;
     H.n_loss = n_loss;
@@ -714,7 +765,7 @@ const char *mt_last_error(void) { return g_err.c_str(); }
 void mt_release(void) {
     std::lock_guard<std::mutex> lk(g.mu);
     drop_graphs();
-    for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.box4, &g.material, &g.bfield,
+    for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.alias, &g.box4, &g.material, &g.bfield,
                       &g.magnet, &g.slab_z, &g.slab_mask, &g.map, &g.queue, &g.partial,
                       &g.scratch, &g.gs_lane, &g.zero_dummy})
         b->release();

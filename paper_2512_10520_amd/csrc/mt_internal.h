@@ -22,6 +22,7 @@ struct DevHist {
     const uint32_t *guide;       // nullptr: search the whole row
     const uint32_t *totals;      // [n_hist]
     const double *edges2;        // [n_pbin + 1] squared momentum edges
+    const uint2 *alias;          // [h][c] alias method: (24-bit threshold split, alias cell)
     int32_t n_mat, n_pbin, n_loss, n_scat, n_cells, gbits;
     uint32_t nscat_magic;        // floor(2^32 / n_scat) + 1 for exact c / n_scat, c < 2^16
     float loss_lo, loss_w, scat_lo, scat_w;
@@ -58,6 +59,9 @@ struct LdsLayout {
 
 struct DevRun {
     double h;                    // step length
+    int32_t sampler;             // MT_SAMPLER_*
+    int32_t interp;              // MT_INTERP_*
+    int32_t stage_field;         // 0: field held from the step start, 1: at every RK4 stage
     double pmin2;
     int32_t max_steps;
     uint32_t key0, key1;

@@ -16,6 +16,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <array>
+#include <utility>
+
 #include "mt_internal.h"
 
 namespace mt {
@@ -273,6 +276,17 @@ __device__ __forceinline__ int sample_cell(const DevHist &H, const Lds &S, int h
     return lo;
 }
 
+// Alias method: column j = floor(w0 K / 2^32); the 24-bit threshold word x
+// (low bytes of w1, w2, w3, which the jitters and the azimuth leave unused)
+// keeps cell j when x is below the column's split, else gives its alias.
+// One 8-byte load per draw.
+__device__ __forceinline__ int alias_cell(const DevHist &H, int h, uint4 w) {
+    const uint32_t j = __umulhi(w.x, (uint32_t)H.n_cells);
+    const uint2 e = H.alias[(size_t)h * H.n_cells + j];
+    const uint32_t x = (w.y & 0xFFu) | ((w.z & 0xFFu) << 8) | ((w.w & 0xFFu) << 16);
+    return (int)(x < e.x ? j : e.y);
+}
+
 // ---------------------------------------------------------------------------
 // Kick: p <- p + R(p_hat) (|p| u), u = (tau cos phi, tau sin phi, -f).  The
 // rotation maps the local z axis onto p_hat, so the loss part is exactly
@@ -383,6 +397,22 @@ __device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const 
     return add_map<MAP>(T, box_field(T, S, R, vol, var), x, y, z);
 }
 
+// Nearest-node lookup of the map: the node closest to (x, y, z) on every axis
+// (half-way points take the higher node), zero outside the grid.  One
+// 16-byte load.
+__device__ __forceinline__ float3 map_nearest(const DevField &F, double x, double y, double z) {
+    const double u = (x - F.lo[0]) * F.inv_d[0];
+    const double v = (y - F.lo[1]) * F.inv_d[1];
+    const double w = (z - F.lo[2]) * F.inv_d[2];
+    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
+          w >= 0.0 && w <= (double)(F.nz - 1)))
+        return make_float3(0.f, 0.f, 0.f);
+    const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
+              k = min((int)(w + 0.5), F.nz - 1);
+    const float4 b = F.map[((size_t)k * F.ny + j) * F.nx + i];
+    return make_float3(b.x, b.y, b.z);
+}
+
 // ---------------------------------------------------------------------------
 // RK4 over arc length with B frozen: dr/ds = p/|p|, dp/ds = kappa q (p/|p|) x B.
 // FP32 stages, increments added to the FP64 state.
@@ -458,13 +488,88 @@ __device__ __forceinline__ void rk4(Lane &L, float3 B, const StepConst &c) {
     rk4_from(L, stage0(L), B, c);
 }
 
+// Compile-time features of a transport kernel (bit mask).
+enum : unsigned {
+    kMap = 1u,       // a field map is loaded
+    kTape = 2u,      // write checkpoints and the kick tape (differentiable form)
+    kTrace = 4u,     // per-step (volume, bin, cell) trace of the first lanes
+    kAlias = 8u,     // alias-method sampler instead of the inverse CDF
+    kNearest = 16u,  // nearest-node map lookup instead of trilinear (with kMap)
+    kStages = 32u,   // field evaluated at every RK4 stage position
+    kFeatures = 64u  // number of masks
+};
+
+// Masks that have a kernel: the tape belongs to the differentiable form,
+// whose adjoint holds the trilinear field over each step, and the
+// nearest-node lookup needs a map.
+constexpr bool valid_mask(unsigned F) {
+    return !((F & kTape) && (F & (kNearest | kStages))) && !((F & kNearest) && !(F & kMap));
+}
+
+// Map part of the field at a point.
+template <unsigned F>
+__device__ __forceinline__ float3 map_field(const Tables &T, float3 B, double x, double y,
+                                            double z) {
+    if constexpr ((F & kNearest) != 0) {
+        const float3 m = map_nearest(T.field, x, y, z);
+        return make_float3(B.x + m.x, B.y + m.y, B.z + m.z);
+    } else {
+        return add_map<(F & kMap) != 0>(T, B, x, y, z);
+    }
+}
+
+// Field at a stage point: scaled field of the box holding it plus the map.
+template <unsigned F>
+__device__ __forceinline__ float3 field_at_point(const Tables &T, const Lds &S, const DevRun &R,
+                                                 const Lane &L, double x, double y, double z) {
+    const int s = find_slab(S, T.geom.n_slab, z, L.slab);
+    const int vol = find_box(S, s, x, y);
+    float3 B;
+    if (vol == L.bvol) B = make_float3(L.bx, L.by, L.bz);
+    else B = box_field(T, S, R, vol, L.var);
+    return map_field<F>(T, B, x, y, z);
+}
+
+// RK4 with the field evaluated afresh at each stage position (stage s sits
+// at r + c_s h v_{s-1}, c = 1/2, 1/2, 1); B1 is the step-start field.
+template <unsigned F>
+__device__ __forceinline__ void rk4_stages(Lane &L, float3 B1, const Tables &T, const Lds &S,
+                                           const DevRun &R, const StepConst &c) {
+    const float kq = (float)kKappa * L.q;
+    const float3 a0 = stage0(L);
+    const float3 n0 = scale3(__builtin_amdgcn_rsqf(norm2(a0)), a0);
+    const float3 k1 = cross3(n0, scale3(kq, B1));
+    const float3 a1 = axpy(c.h2, k1, a0);
+    const float3 n1 = scale3(__builtin_amdgcn_rsqf(norm2(a1)), a1);
+    const float3 B2 = field_at_point<F>(T, S, R, L, L.x + (double)(c.h2 * n0.x),
+                                        L.y + (double)(c.h2 * n0.y), L.z + (double)(c.h2 * n0.z));
+    const float3 k2 = cross3(n1, scale3(kq, B2));
+    const float3 a2 = axpy(c.h2, k2, a0);
+    const float3 n2 = scale3(__builtin_amdgcn_rsqf(norm2(a2)), a2);
+    const float3 B3 = field_at_point<F>(T, S, R, L, L.x + (double)(c.h2 * n1.x),
+                                        L.y + (double)(c.h2 * n1.y), L.z + (double)(c.h2 * n1.z));
+    const float3 k3 = cross3(n2, scale3(kq, B3));
+    const float3 a3 = axpy(c.h, k3, a0);
+    const float3 n3 = scale3(__builtin_amdgcn_rsqf(norm2(a3)), a3);
+    const float3 B4 = field_at_point<F>(T, S, R, L, L.x + (double)(c.h * n2.x),
+                                        L.y + (double)(c.h * n2.y), L.z + (double)(c.h * n2.z));
+    const float3 k4 = cross3(n3, scale3(kq, B4));
+    L.px += (double)(c.h6 * (fmaf(2.0f, k2.x + k3.x, k1.x) + k4.x));
+    L.py += (double)(c.h6 * (fmaf(2.0f, k2.y + k3.y, k1.y) + k4.y));
+    L.pz += (double)(c.h6 * (fmaf(2.0f, k2.z + k3.z, k1.z) + k4.z));
+    L.x += (double)(c.h6 * (fmaf(2.0f, n1.x + n2.x, n0.x) + n3.x));
+    L.y += (double)(c.h6 * (fmaf(2.0f, n1.y + n2.y, n0.y) + n3.y));
+    L.z += (double)(c.h6 * (fmaf(2.0f, n1.z + n2.z, n0.z) + n3.z));
+}
+
 // ---------------------------------------------------------------------------
 // One iteration of the transport loop.  Returns false (with L.status set)
 // when a break condition holds at the top of the iteration.
 // ---------------------------------------------------------------------------
-template <bool MAP, bool TAPE, bool TRACE>
+template <unsigned F>
 __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, const DevRun &R,
                                         const StepConst &sc) {
+    constexpr bool MAP = (F & kMap) != 0, TAPE = (F & kTape) != 0, TRACE = (F & kTrace) != 0;
     const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
     // Break test in the order p_min, z_max, x_max, y_max, step cap (the first
     // that holds decides the status).
@@ -485,7 +590,8 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         const int ibin = bin_of(L, T, S, p2);
         const uint4 w = philox_step(L.ph, (uint32_t)L.k, R.key0, R.key1);
         const int h = mat * T.hist.n_pbin + ibin;
-        cell = sample_cell(T.hist, S, h, w.x);
+        if constexpr ((F & kAlias) != 0) cell = alias_cell(T.hist, h, w);
+        else cell = sample_cell(T.hist, S, h, w.x);
         const int il = (int)__umulhi((uint32_t)cell, T.hist.nscat_magic);
         const int is = cell - il * T.hist.n_scat;
         const float v1 = (float)(w.y >> 8) * 0x1p-24f;
@@ -518,8 +624,9 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         L.bz = b.z;
         L.bvol = vol;
     }
-    const float3 B = add_map<MAP>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
-    rk4(L, B, sc);
+    const float3 B = map_field<F>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
+    if constexpr ((F & kStages) != 0) rk4_stages<F>(L, B, T, S, R, sc);
+    else rk4(L, B, sc);
     ++L.k;
     return true;
 }
@@ -560,8 +667,9 @@ __device__ __forceinline__ void write_ckpt(const Lane &L, const DevRun &R) {
 // ---------------------------------------------------------------------------
 // Plain form: one lane per (variant, muon) until it stops.
 // ---------------------------------------------------------------------------
-template <bool MAP, bool CKPT, bool TRACE>
+template <unsigned F>
 __global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
+    constexpr bool CKPT = (F & kTape) != 0;
     extern __shared__ __align__(16) char smem[];
     const Lds S = stage_tables(smem, T);
     const StepConst sc = step_const(R);
@@ -572,7 +680,7 @@ __global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
     if (L.status == MT_ST_RUNNING) {
         for (;;) {
             if (CKPT && (L.k % kCkptEvery) == 0 && L.k < R.max_steps) write_ckpt(L, R);
-            if (!advance<MAP, CKPT, TRACE>(L, T, S, R, sc)) break;
+            if (!advance<F>(L, T, S, R, sc)) break;
         }
     }
     store_lane(L, T, S, io);
@@ -636,7 +744,7 @@ __device__ __forceinline__ void unpack_rec(Lane &L, const MoveRec &m, int32_t k,
     L.e2hi = -INFINITY;
 }
 
-template <bool MAP, bool TRACE>
+template <unsigned F>     // F never holds kTape
 __global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO io, int compact,
                                                      unsigned long long *queue) {
     extern __shared__ __align__(16) char smem[];
@@ -665,7 +773,7 @@ __global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO i
         for (;;) {
             if (wave * kWave < n_busy) {
                 for (int c = 0; c < compact; ++c) {
-                    if (active && !advance<MAP, false, TRACE>(L, T, S, R, sc)) {
+                    if (active && !advance<F>(L, T, S, R, sc)) {
                         store_lane(L, T, S, io);
                         active = false;
                     }
@@ -1064,43 +1172,65 @@ __global__ void k_pass2(const double *partial, int nb, int n_cols, int n_variant
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+template <unsigned F>
+static const void *plain_kernel() {
+    if constexpr (valid_mask(F)) return reinterpret_cast<const void *>(&k_plain<F>);
+    else return nullptr;
+}
+
+template <unsigned F>
+static const void *persistent_kernel() {
+    if constexpr (valid_mask(F) && !(F & kTape))
+        return reinterpret_cast<const void *>(&k_persistent<F>);
+    else return nullptr;
+}
+
+template <size_t... I>
+static std::array<const void *, sizeof...(I)> plain_kernels(std::index_sequence<I...>) {
+    return {plain_kernel<(unsigned)I>()...};
+}
+
+template <size_t... I>
+static std::array<const void *, sizeof...(I)> persistent_kernels(std::index_sequence<I...>) {
+    return {persistent_kernel<(unsigned)I>()...};
+}
+
+static unsigned feature_mask(const Tables &T, const DevRun &R) {
+    const bool map = T.field.map != nullptr;
+    return (map ? kMap : 0u) | (R.ckpt != nullptr ? kTape : 0u) |
+           (R.n_trace > 0 ? kTrace : 0u) | (R.sampler == MT_SAMPLER_ALIAS ? kAlias : 0u) |
+           (map && R.interp == MT_INTERP_NEAREST ? kNearest : 0u) |
+           (R.stage_field ? kStages : 0u);
+}
+
 hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,
                         hipStream_t s) {
+    static const auto fns = plain_kernels(std::make_index_sequence<kFeatures>());
     if (R.lanes == 0) return hipSuccess;
     const unsigned grid = (unsigned)((R.lanes + block - 1) / block);
-    const bool map = T.field.map != nullptr;
-    const bool ck = R.ckpt != nullptr;
-    const bool tr = R.n_trace > 0;
-    const size_t shm = (size_t)T.lds.bytes;
-#define MT_PLAIN(A, B, C) \
-    hipLaunchKernelGGL((k_plain<A, B, C>), dim3(grid), dim3(block), shm, s, T, R, io)
-    if (map) {
-        if (ck) { if (tr) MT_PLAIN(true, true, true); else MT_PLAIN(true, true, false); }
-        else { if (tr) MT_PLAIN(true, false, true); else MT_PLAIN(true, false, false); }
-    } else {
-        if (ck) { if (tr) MT_PLAIN(false, true, true); else MT_PLAIN(false, true, false); }
-        else { if (tr) MT_PLAIN(false, false, true); else MT_PLAIN(false, false, false); }
-    }
-#undef MT_PLAIN
-    return hipGetLastError();
+    Tables t = T;
+    DevRun r = R;
+    DevIO o = io;
+    void *args[] = {&t, &r, &o};
+    const void *fn = fns[feature_mask(T, R)];
+    if (fn == nullptr) return hipErrorInvalidValue;     // excluded by argument validation
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, (size_t)T.lds.bytes, s);
 }
 
 static size_t persistent_lds(const Tables &T, int block) {
     return (size_t)((T.lds.bytes + 15) & ~15) + (size_t)block * sizeof(MoveRec);
 }
 
-static const void *persistent_fn(bool map, bool trace) {
-    if (map) return trace ? reinterpret_cast<const void *>(k_persistent<true, true>)
-                          : reinterpret_cast<const void *>(k_persistent<true, false>);
-    return trace ? reinterpret_cast<const void *>(k_persistent<false, true>)
-                 : reinterpret_cast<const void *>(k_persistent<false, false>);
+static const void *persistent_fn(unsigned mask) {
+    static const auto fns = persistent_kernels(std::make_index_sequence<kFeatures>());
+    return fns[mask];
 }
 
 int persistent_blocks_per_cu(const Tables &T, int block) {
     int n = 0;
-    // The register footprint of the trace-free form sets the grid.
+    // The register footprint of the trace-free inverse-CDF form sets the grid.
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, persistent_fn(T.field.map != nullptr, false), block, persistent_lds(T, block));
+        &n, persistent_fn(T.field.map != nullptr ? kMap : 0u), block, persistent_lds(T, block));
     if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
@@ -1109,15 +1239,16 @@ hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, 
                              int grid, int compact_every, unsigned long long *queue,
                              hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
-    const size_t shm = persistent_lds(T, block);
-    const bool map = T.field.map != nullptr, tr = R.n_trace > 0;
-#define MT_PERS(A, B) \
-    hipLaunchKernelGGL((k_persistent<A, B>), dim3(grid), dim3(block), shm, s, T, R, io, \
-                       compact_every, queue)
-    if (map) { if (tr) MT_PERS(true, true); else MT_PERS(true, false); }
-    else { if (tr) MT_PERS(false, true); else MT_PERS(false, false); }
-#undef MT_PERS
-    return hipGetLastError();
+    Tables t = T;
+    DevRun r = R;
+    DevIO o = io;
+    int c = compact_every;
+    unsigned long long *q = queue;
+    void *args[] = {&t, &r, &o, &c, &q};
+    const void *fn = persistent_fn(feature_mask(T, R) & ~kTape);
+    if (fn == nullptr) return hipErrorInvalidValue;     // excluded by argument validation
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(block), args, persistent_lds(T, block),
+                           s);
 }
 
 hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero,

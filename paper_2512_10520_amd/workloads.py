@@ -186,12 +186,17 @@ class Geometry:
     z_max)`` are the break conditions |x| >= x_max, |y| >= y_max, z >= z_max.
     """
 
-    box: np.ndarray              # float64 [n][6]
+    box: np.ndarray              # float64 [n][6] ([0][6] when ``poly`` is given)
     material: np.ndarray         # int32 [n]
     b_box: np.ndarray            # float32 [n][3]
     magnet: np.ndarray           # int32 [n]
     n_mag: int
     world: np.ndarray            # float64 [3]
+    # Convex blocks instead of boxes: [n][18] = z_lo, z_hi, the quadrilateral
+    # at z_lo as (x, y) x 4, the one at z_hi (same vertex order).  The slice
+    # at height z interpolates the two; containment is the sign test of the
+    # edge cross products, half-open in z; lowest index wins.
+    poly: Optional[np.ndarray] = None
 
 
 @dataclass
@@ -355,6 +360,8 @@ class RunParams:
     n_variants: int = 1
     scales: Optional[np.ndarray] = None   # float32 [n_variants][n_mag] or None (= 1)
     sampler: int = 0             # 0 inverse CDF, 1 alias method
+    interp: int = 0              # field map lookup: 0 trilinear, 1 nearest node
+    stage_field: int = 0         # 0 field held from the step start, 1 at every RK4 stage
 
 
 @dataclass

@@ -13,7 +13,8 @@ int main(void) {
     F(mt_params, compact_every); F(mt_params, use_graph); F(mt_params, ckpt_every);
     F(mt_params, ckpt); F(mt_params, tape); F(mt_params, trace); F(mt_params, n_trace);
     F(mt_params, trace_steps); F(mt_params, tally); F(mt_params, z_det); F(mt_params, r_ap);
-    F(mt_params, r_scale);
+    F(mt_params, r_scale); F(mt_params, sampler); F(mt_params, interp);
+    F(mt_params, stage_field);
     printf("mt_muons sizeof %zu\n", sizeof(mt_muons));
     F(mt_muons, x); F(mt_muons, y); F(mt_muons, z); F(mt_muons, px); F(mt_muons, py);
     F(mt_muons, pz); F(mt_muons, q);

@@ -1,0 +1,77 @@
+"""GPU parity of the two field options against the oracle: the map read by
+nearest-node lookup (Section "Simulation", item 3) and the field evaluated
+at every RK4 stage position (box lookup and map at the stage point).
+
+Both add decisions that the (volume, bin, cell) trace does not record: which
+node is nearest, and which box holds a stage point.  The oracle folds their
+margins (distance to a mid-plane between nodes, to a box face or to the map's
+edge, at every point where the field is read) into each muon's minimum
+margin, so these tests use the whole-trajectory tie rule, with a looser bound
+on the fraction of tie muons for the long shield paths (a node choice is a
+decision at every step inside the map)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2512_10520_amd import workloads as W
+from tests._parity import compare, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    from paper_2512_10520_amd import _lib
+    _lib.load()
+
+
+def _with(wl, **kw):
+    return dataclasses.replace(wl, run=dataclasses.replace(wl.run, **kw))
+
+
+@pytest.mark.parametrize("interp,stage", [(1, 0), (0, 1), (1, 1)],
+                         ids=["nearest", "stages", "nearest+stages"])
+def test_shield_field_modes(interp, stage):
+    wl = _with(W.make_workload("shield", n_muons=2000), interp=interp, stage_field=stage)
+    n = len(wl.muons)
+    o = oracle_run(wl, np.arange(n))
+    g = gpu_run(wl)
+    s = compare(g, o, max_tie_frac=0.05, label=f"shield interp={interp} stages={stage}")
+    print("shield", interp, stage, s)
+    gp = gpu_run(wl, mode="persistent")
+    for k in ("state", "status", "n_steps", "volume"):
+        assert np.array_equal(g[k], gp[k]), k
+    # the option changes the transport (same random streams, different field)
+    base = gpu_run(W.make_workload("shield", n_muons=2000))
+    assert not np.array_equal(base["state"], g["state"])
+
+
+@pytest.mark.parametrize("name,n", [("block", 20_011), ("scan", 3000)])
+def test_stage_field_box_geometries(name, n):
+    """Uniform box fields: stage points that cross a box face (the entry face
+    at z = 0, the slab faces of the 8-magnet scan) take the neighbour's field."""
+    wl = _with(W.make_workload(name, n_muons=n, **({"n_variants": 2} if name == "scan" else {})),
+               stage_field=1)
+    g = gpu_run(wl, trace_steps=260, n_trace=1000)
+    for v in range(wl.run.n_variants):
+        o = oracle_run(wl, np.arange(n), variant=v, trace_steps=260)
+        sel = np.arange(v * n, (v + 1) * n)
+        s = compare(g, o, sel=sel, label=f"{name} stages v={v}")
+        print(name, "stages", v, s)
+
+
+def test_field_modes_rejected_with_checkpoints():
+    import torch
+    from paper_2512_10520_amd import api
+    wl = W.make_workload("diff", n_muons=64)
+    api.load_workload(wl)
+    dm = api.DeviceMuons.from_host(wl.muons)
+    sc = torch.ones((1, wl.geom.n_mag), dtype=torch.float32, device="cuda")
+    for kw in ({"interp": "nearest"}, {"stage_field": True}):
+        spec = api.RunSpec.from_workload(wl, **kw)
+        with pytest.raises(RuntimeError, match="differentiable form"):
+            api.propagate(dm, spec, scales=sc, ckpt=True)

@@ -442,3 +442,175 @@ def test_per_box_field_scaled_by_magnet_and_added_to_map():
     res = oracle.propagate(wl)
     ex = _exact_uniform(mu.stacked()[:, 0], 1, 0.8 * 1.0 + 0.5, 0.02)
     assert np.allclose(res.state[:, 0], ex, atol=1e-12)
+
+
+# ------------------------------------------------------- nearest-node map and per-stage field
+def test_nearest_node_matches_brute_force():
+    """The nearest-node lookup returns the value of the grid node at the
+    smallest Euclidean distance (found by scanning every node), node values at
+    nodes, the higher node at an exact mid-point, and zero outside."""
+    rng = np.random.default_rng(8)
+    lo, hi = np.array([0.0, -1.0, 2.0]), np.array([4.0, 1.0, 5.0])
+    nx, ny, nz = 5, 3, 4
+    vals = rng.normal(size=(nz, ny, nx, 3)).astype(np.float32)
+    fmap = W.FieldMap(lo=lo, hi=hi, b=vals)
+    wl = CU.workload(CU.flat_histograms(), CU.geometry(np.zeros((0, 6)), np.zeros(0)),
+                     CU.muons(0, 0, 0, 0, 0, 1, 1), field=fmap, interp=1)
+    xs, ys, zs = (np.linspace(lo[a], hi[a], n) for a, n in enumerate((nx, ny, nz)))
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    nodes = np.stack([X, Y, Z], axis=-1).reshape(-1, 3)
+    flat = vals.reshape(-1, 3).astype(np.float64)
+    for _ in range(500):
+        r = rng.uniform(lo, hi)
+        k = np.argmin(np.linalg.norm(nodes - r, axis=1))
+        assert np.array_equal(oracle.nearest(wl, r), flat[k])
+    for k in range(len(nodes)):
+        assert np.array_equal(oracle.nearest(wl, nodes[k]), flat[k])
+    # exact mid-point between x nodes 0 and 1 (x = 0.5): the higher node
+    r = np.array([0.5, -1.0, 2.0])
+    assert np.array_equal(oracle.nearest(wl, r), flat[1])
+    for r in ([4.0001, 0, 3], [0, -1.5, 3], [1, 0, 1.99], [1, 0, 5.01]):
+        assert np.array_equal(oracle.nearest(wl, r), np.zeros(3))
+
+
+def _scaled_affine_map():
+    A, b, fmap = _affine_map()
+    return A / 8, b / 8, W.FieldMap(lo=fmap.lo, hi=fmap.hi, b=(fmap.b / 8).astype(np.float32))
+
+
+def _reference_path(y0, q, A, b, length):
+    """dr/ds = p/|p|, dp/ds = kappa q (p/|p|) x (A r + b), by an adaptive
+    8th-order integrator at tight tolerance."""
+    from scipy.integrate import solve_ivp
+
+    def f(s, y):
+        u = y[3:] / np.linalg.norm(y[3:])
+        return np.concatenate([u, oracle.KAPPA * q * np.cross(u, A @ y[:3] + b)])
+
+    sol = solve_ivp(f, (0, length), y0, method="DOP853", rtol=1e-13, atol=1e-13)
+    return sol.y[:, -1]
+
+
+@pytest.mark.parametrize("stage_field,order", [(1, 4), (0, 1)])
+def test_rk4_convergence_order_in_position_dependent_field(stage_field, order):
+    """In a field that varies along the path, RK4 with the field evaluated at
+    every stage converges at fourth order in the step; holding the step-start
+    field over the step drops the method to first order.  Reference: an
+    independent adaptive integrator of the same equation of motion."""
+    A, b, fmap = _scaled_affine_map()
+    geom = CU.geometry(np.zeros((0, 6)), np.zeros(0), world=(50.0, 50.0, 100.0))
+    y0 = np.array([0.1, -0.2, 1.0, 0.4, -0.3, 2.0])
+    length = 3.2
+    ref = _reference_path(y0, 1.0, A, b, length)
+    errs = []
+    for h in (0.16, 0.08, 0.04):
+        mu = CU.muons(*y0, 1)
+        wl = CU.workload(CU.flat_histograms(), geom, mu, step=h, max_steps=int(round(length / h)),
+                         p_min=0.01, field=fmap, stage_field=stage_field)
+        res = oracle.propagate(wl)
+        assert res.status[0] == oracle.ST_STEPS
+        errs.append(np.linalg.norm(res.state[:, 0] - ref))
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    print("errors", errs, "ratios", ratios)
+    expect = 2.0 ** order
+    assert all(0.75 * expect < r < 1.35 * expect for r in ratios), ratios
+
+
+def test_stage_field_equals_held_field_in_one_uniform_box():
+    """With one uniform box field and no map the stage evaluations all return
+    the step-start field, so both forms give the same bits."""
+    geom = CU.geometry([[-5, 5, -5, 5, -1, 50]], [-1], b_box=[[0.3, 1.7, -0.2]],
+                       world=(5.0, 5.0, 40.0))
+    mu = CU.muons([0.0, 0.2], [0.1, -0.3], 0.0, [0.2, -0.1], [0.1, 0.0], [5.0, 20.0], [1, -1])
+    a = oracle.propagate(CU.workload(CU.flat_histograms(), geom, mu, max_steps=300, p_min=0.1))
+    b = oracle.propagate(CU.workload(CU.flat_histograms(), geom, mu, max_steps=300, p_min=0.1,
+                                     stage_field=1))
+    assert np.array_equal(a.state, b.state) and np.array_equal(a.n_steps, b.n_steps)
+
+
+# ------------------------------------------------------- convex blocks (sign test)
+def _block(zlo, zhi, bottom, top):
+    return np.concatenate([[zlo, zhi], np.asarray(bottom, float).ravel(),
+                           np.asarray(top, float).ravel()])
+
+
+def test_block_with_equal_rectangles_is_a_box():
+    """A block whose two end quads are the same axis-aligned rectangle holds
+    the same points as the box (away from the x-y faces, where the sign test
+    is closed and the box half-open)."""
+    rng = np.random.default_rng(11)
+    box = [-0.7, 1.3, -0.4, 0.9, 0.5, 2.5]
+    rect = [[box[0], box[2]], [box[1], box[2]], [box[1], box[3]], [box[0], box[3]]]
+    blk = _block(box[4], box[5], rect, rect)
+    for _ in range(2000):
+        r = rng.uniform([-1.5, -1.0, 0.0], [2.0, 1.5, 3.0])
+        inb = (box[0] <= r[0] < box[1]) and (box[2] <= r[1] < box[3]) and (box[4] <= r[2] < box[5])
+        assert oracle.poly_inside(blk, r) == inb
+    assert oracle.poly_inside(blk, [0.0, 0.0, 0.5]) and not oracle.poly_inside(blk, [0.0, 0.0, 2.5])
+
+
+@pytest.mark.parametrize("orient", [1, -1])
+def test_pyramid_frustum_matches_convex_hull(orient):
+    """A frustum cut from a pyramid has planar faces, so it is the convex hull
+    of its eight corners: containment by the sign test of the interpolated
+    slice equals containment in the hull (Delaunay simplex search), with the
+    vertices listed either way round."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(12)
+    bottom = np.array([[-1.0, -0.8], [1.2, -0.6], [0.9, 1.1], [-0.7, 0.9]])[::orient]
+    apex = np.array([0.3, 0.2, 6.0])
+    z0, z1 = 1.0, 3.5
+    top = apex[:2] + (z1 - apex[2]) / (z0 - apex[2]) * (bottom - apex[:2])
+    blk = _block(z0, z1, bottom, top)
+    corners = np.vstack([np.column_stack([bottom, np.full(4, z0)]),
+                         np.column_stack([top, np.full(4, z1)])])
+    hull = Delaunay(corners)
+    n_in = 0
+    for _ in range(4000):
+        r = rng.uniform([-1.5, -1.2, 0.5], [1.7, 1.6, 4.0])
+        if not (z0 < r[2] < z1):
+            assert not oracle.poly_inside(blk, r) or r[2] == z0
+            continue
+        expect = hull.find_simplex(r) >= 0
+        got = oracle.poly_inside(blk, r)
+        n_in += got
+        assert got == expect, r
+    assert n_in > 500
+
+
+def test_twisted_block_slice_by_areas():
+    """Non-planar sides (top quad rotated against the bottom): at every height
+    the block holds exactly the points of the interpolated convex slice,
+    checked by triangle areas (a point inside a convex polygon splits it into
+    triangles whose areas add up to the polygon's)."""
+    rng = np.random.default_rng(13)
+    sq = np.array([[-1.0, -1.0], [1.0, -1.0], [1.0, 1.0], [-1.0, 1.0]])
+    c, s = np.cos(0.5), np.sin(0.5)
+    top = 0.6 * sq @ np.array([[c, s], [-s, c]]) + [0.2, -0.1]
+    blk = _block(0.0, 2.0, sq, top)
+
+    def area(poly):
+        x, y = poly[:, 0], poly[:, 1]
+        return 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1)))
+
+    for _ in range(3000):
+        r = rng.uniform([-1.3, -1.3, 0.0], [1.3, 1.3, 2.0])
+        t = r[2] / 2.0
+        v = (1 - t) * sq + t * top
+        tri = sum(area(np.array([r[:2], v[i], v[(i + 1) % 4]])) for i in range(4))
+        A = area(v)
+        if abs(tri - A) < 1e-9 * A or tri - A > 1e-6 * A:      # skip points near an edge
+            assert oracle.poly_inside(blk, r) == (abs(tri - A) < 1e-9 * A)
+
+
+def test_overlapping_blocks_lowest_index():
+    rect = np.array([[0.0, 0.0], [2.0, 0.0], [2.0, 2.0], [0.0, 2.0]])
+    b0 = _block(0.0, 1.0, rect, rect)
+    b1 = _block(0.5, 3.0, rect + 1.0, rect + 1.0)
+    geom = CU.geometry(None, [1, 2], world=(10.0, 10.0, 10.0), poly=np.stack([b0, b1]))
+    wl = CU.workload(CU.flat_histograms(), geom, CU.muons(0, 0, 0, 0, 0, 1, 1))
+    assert oracle.lookup(wl, [1.5, 1.5, 0.7]) == 0            # in both: lowest index
+    assert oracle.lookup(wl, [2.5, 2.5, 0.7]) == 1
+    assert oracle.lookup(wl, [1.5, 1.5, 1.2]) == 1
+    assert oracle.lookup(wl, [0.5, 0.5, 1.2]) == -1
+    assert oracle.lookup(wl, [1.5, 1.5, 3.0]) == -1           # half-open in z
