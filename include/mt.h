@@ -123,6 +123,28 @@ int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material,
                      const double *world);
 
 /*
+ * Geometry of convex blocks (Section "Simulation", item 1, Eq. (1)); replaces
+ * any loaded geometry.  Block b spans z_lo <= z < z_hi; its cross-section at
+ * height z is the quadrilateral whose vertices interpolate linearly between
+ * the quad at z_lo and the quad at z_hi (t = (z - z_lo) / (z_hi - z_lo)).  A
+ * point is inside when the edge cross products S_i = e_ix (y - v_iy) -
+ * e_iy (x - v_ix) of that slice are all >= 0 or all <= 0; overlapping blocks
+ * resolve to the lowest index.  Candidates are pruned with a uniform grid
+ * (at most 1024 cells) over the blocks' bounding box.
+ *
+ *   block     host double [n][18] = z_lo, z_hi, (x, y) of the 4 vertices at
+ *             z_lo, (x, y) of the same 4 vertices at z_hi.  Both quads must
+ *             be strictly convex and listed in the same rotational order (the
+ *             mid-height slice is checked too).
+ *   material, b_box, magnet, n_mag, world: as for mt_load_geometry, per block.
+ * Limits: 1 <= n <= MT_MAX_BOXES.  The differentiable form and the per-stage
+ * field (stage_field = 1) need box geometry.
+ * Errors: MT_ERR_INVALID_ARG, MT_ERR_LIMIT, MT_ERR_OOM, MT_ERR_HIP.
+ */
+int mt_load_blocks(int32_t n, const double *block, const int32_t *material, const float *b_box,
+                   const int32_t *magnet, int32_t n_mag, const double *world);
+
+/*
  * Field map on a regular 3D grid (Section "Simulation", item 3), added to
  * the per-box field and interpolated trilinearly.  Node (i, j, k) sits at
  * lo + (i, j, k) * (hi - lo) / (n - 1); outside [lo, hi] the map gives zero.

@@ -23,7 +23,8 @@ ST_RUNNING, ST_PMIN, ST_ZMAX, ST_XMAX, ST_YMAX, ST_MAXSTEPS, ST_INVALID = range(
 CKPT_EVERY = 16
 
 # Names of every entry point the header declares (checked by the CPU tests).
-EXPORTS = ("mt_load_histograms", "mt_load_geometry", "mt_load_field", "mt_propagate",
+EXPORTS = ("mt_load_histograms", "mt_load_geometry", "mt_load_blocks", "mt_load_field",
+           "mt_propagate",
            "mt_propagate_backward", "mt_autotune", "mt_last_error", "mt_release",
            "mt_device_info")
 
@@ -66,6 +67,7 @@ def load():
             vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
             L.mt_load_histograms.argtypes = [i32, i32, vp, i32, dbl, dbl, i32, dbl, dbl, vp]
             L.mt_load_geometry.argtypes = [i32, vp, vp, vp, vp, i32, vp]
+            L.mt_load_blocks.argtypes = [i32, vp, vp, vp, vp, i32, vp]
             L.mt_load_field.argtypes = [i32, i32, i32, vp, vp, vp]
             L.mt_propagate.argtypes = [C.POINTER(MtParams), i64, C.POINTER(MtMuons),
                                        C.POINTER(MtMuons), C.POINTER(MtResult), vp]

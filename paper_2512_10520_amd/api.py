@@ -52,16 +52,23 @@ _loaded = {"n_mag": 0}
 
 
 def load_geometry(geom) -> None:
+    """Load a ``workloads.Geometry``: boxes (``mt_load_geometry``) or, when
+    ``geom.poly`` is set, convex blocks (``mt_load_blocks``)."""
     L = _lib.load()
-    box = _host(geom.box, np.float64).reshape(-1, 6)
     mat = _host(geom.material, np.int32)
     bb = None if geom.b_box is None else _host(geom.b_box, np.float32)
     mag = None if geom.magnet is None else _host(geom.magnet, np.int32)
     world = _host(geom.world, np.float64)
-    check(L.mt_load_geometry(len(mat), box.ctypes.data, mat.ctypes.data,
-                             None if bb is None else bb.ctypes.data,
-                             None if mag is None else mag.ctypes.data, int(geom.n_mag),
-                             world.ctypes.data))
+    bbp = None if bb is None else bb.ctypes.data
+    magp = None if mag is None else mag.ctypes.data
+    if getattr(geom, "poly", None) is not None:
+        blk = _host(geom.poly, np.float64).reshape(-1, 18)
+        check(L.mt_load_blocks(len(mat), blk.ctypes.data, mat.ctypes.data, bbp, magp,
+                               int(geom.n_mag), world.ctypes.data))
+    else:
+        box = _host(geom.box, np.float64).reshape(-1, 6)
+        check(L.mt_load_geometry(len(mat), box.ctypes.data, mat.ctypes.data, bbp, magp,
+                                 int(geom.n_mag), world.ctypes.data))
     _loaded["n_mag"] = int(geom.n_mag)
 
 

@@ -85,7 +85,7 @@ struct State {
     bool hist_loaded = false, geom_loaded = false;
     int n_mat = 0, n_pbin = 0;
     int64_t version = 0;  // bumped on every table change
-    DevBuf cdf, guide, totals, edges2, alias;
+    DevBuf cdf, guide, totals, edges2, alias, blk, grid;
     DevBuf box4, material, bfield, magnet, slab_z, slab_mask;
     DevBuf map;
     DevBuf queue, partial, scratch, gs_lane, zero_dummy;
@@ -136,10 +136,13 @@ void relayout() {
         return o;
     };
     const int P = g.T.hist.n_pbin, nb = g.T.geom.n_box, ns = g.T.geom.n_slab;
+    const int np = g.T.geom.n_poly;
     const int nh = g.T.hist.n_mat * P;
     L.off_e2 = take(8 * (P + 1), 16);
     L.off_tot = take(4 * nh, 16);
-    L.off_box4 = take(32 * nb, 16);
+    L.off_box4 = take(np > 0 ? 0 : 32 * nb, 16);
+    L.off_blk = take(8 * mt::kBlockRec * np, 16);
+    L.off_grid = take(np > 0 ? 8 * g.T.geom.gx * g.T.geom.gy * g.T.geom.gz : 0, 16);
     L.off_bf = take(16 * nb, 16);
     L.off_mat = take(4 * nb, 16);
     L.off_mag = take(4 * nb, 16);
@@ -196,6 +199,9 @@ int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *
     if (p->ckpt_every != 0 && (p->interp != MT_INTERP_TRILINEAR || p->stage_field != 0))
         return fail(MT_ERR_INVALID_ARG, "the differentiable form (ckpt_every) supports the "
                                         "held trilinear field only");
+    if (g.T.geom.n_poly > 0 && (p->ckpt_every != 0 || p->stage_field != 0))
+        return fail(MT_ERR_INVALID_ARG, "convex-block geometry supports neither the "
+                                        "differentiable form nor stage_field = 1");
     if (p->ckpt_every != 0 && p->ckpt_every != mt::kCkptEvery)
         return fail(MT_ERR_INVALID_ARG, "ckpt_every must be 0 or %d", mt::kCkptEvery);
     if (p->ckpt_every != 0) {
@@ -600,6 +606,7 @@ int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material, 
     if ((rc = g.slab_mask.upload(mask.data(), mask.size() * 8))) return rc;
     mt::DevGeom &G = g.T.geom;
     G.n_box = n_box;
+    G.n_poly = 0;
     G.n_slab = n_slab;
     G.n_mag = n_mag;
     G.disjoint = disjoint ? 1 : 0;
@@ -612,6 +619,168 @@ int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material, 
     G.x_max = world[0];
     G.y_max = world[1];
     G.z_max = world[2];
+    g.max_material = max_mat;
+    g.geom_loaded = true;
+    relayout();
+    tables_changed();
+    return MT_OK;
+}
+
+// Convex blocks (Section "Simulation", item 1).  Each block is stored as
+// kBlockRec doubles: z_lo, z_hi, 1 / (z_hi - z_lo), 0, the quad at z_lo as
+// (x, y) x 4, and the per-vertex change (top - bottom) x 4, so that the
+// slice at height z is bottom + t (top - bottom), t = (z - z_lo) / (z_hi - z_lo).
+// A uniform grid over the blocks' bounding box lists, per cell, the blocks
+// whose bounding box (grown by a small margin) meets the cell: the spatial
+// hashing that prunes candidates before the sign test.
+static double cross_z(const double *a, const double *b, const double *c) {
+    return (b[0] - a[0]) * (c[1] - b[1]) - (b[1] - a[1]) * (c[0] - b[0]);
+}
+
+// +1 / -1: strictly convex quad listed counter-clockwise / clockwise; 0: not convex.
+static int quad_orientation(const double q[8]) {
+    int sgn = 0;
+    for (int i = 0; i < 4; ++i) {
+        const double c = cross_z(q + 2 * i, q + 2 * ((i + 1) % 4), q + 2 * ((i + 2) % 4));
+        const int si = c > 0.0 ? 1 : (c < 0.0 ? -1 : 0);
+        if (si == 0 || (sgn != 0 && si != sgn)) return 0;
+        sgn = si;
+    }
+    return sgn;
+}
+
+int mt_load_blocks(int32_t n, const double *block, const int32_t *material, const float *b_box,
+                   const int32_t *magnet, int32_t n_mag, const double *world) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    int rc = MT_OK;
+    if (n < 1 || n > MT_MAX_BOXES)
+        return fail(n < 1 ? MT_ERR_INVALID_ARG : MT_ERR_LIMIT, "n = %d not in [1, %d]", n,
+                    MT_MAX_BOXES);
+    if (n_mag < 0 || n_mag > MT_MAX_MAGNETS)
+        return fail(n_mag < 0 ? MT_ERR_INVALID_ARG : MT_ERR_LIMIT, "n_mag = %d not in [0, %d]",
+                    n_mag, MT_MAX_MAGNETS);
+    if (!block || !material || !world)
+        return fail(MT_ERR_INVALID_ARG, "block, material and world must be non-NULL");
+    for (int a = 0; a < 3; ++a)
+        if (std::isnan(world[a])) return fail(MT_ERR_INVALID_ARG, "world[%d] is NaN", a);
+    std::vector<double> rec((size_t)mt::kBlockRec * n);
+    std::vector<float4> bf((size_t)n);
+    std::vector<int32_t> mat((size_t)n), mag((size_t)n);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    std::vector<double> bb((size_t)6 * n);
+    int max_mat = -1;
+    for (int b = 0; b < n; ++b) {
+        const double *p = block + 18 * b;
+        for (int i = 0; i < 18; ++i)
+            if (!std::isfinite(p[i]))
+                return fail(MT_ERR_INVALID_ARG, "block %d: coordinates must be finite", b);
+        if (!(p[0] < p[1])) return fail(MT_ERR_INVALID_ARG, "block %d: z_lo must be < z_hi", b);
+        double mid[8];
+        for (int i = 0; i < 8; ++i) mid[i] = 0.5 * (p[2 + i] + p[10 + i]);
+        const int o0 = quad_orientation(p + 2), o1 = quad_orientation(p + 10);
+        if (o0 == 0 || o1 != o0 || quad_orientation(mid) != o0)
+            return fail(MT_ERR_INVALID_ARG, "block %d: end quads must be strictly convex with the "
+                                            "same vertex order", b);
+        double *r = rec.data() + (size_t)mt::kBlockRec * b;
+        r[0] = p[0];
+        r[1] = p[1];
+        r[2] = 1.0 / (p[1] - p[0]);
+        r[3] = 0.0;
+        for (int i = 0; i < 8; ++i) {
+            r[4 + i] = p[2 + i];
+            r[12 + i] = p[10 + i] - p[2 + i];
+        }
+        double *q = bb.data() + 6 * b;
+        q[0] = q[2] = INFINITY;
+        q[1] = q[3] = -INFINITY;
+        for (int i = 0; i < 8; ++i) {
+            const double x = (i < 4 ? p[2 + 2 * i] : p[10 + 2 * (i - 4)]);
+            const double y = (i < 4 ? p[3 + 2 * i] : p[11 + 2 * (i - 4)]);
+            q[0] = std::min(q[0], x);
+            q[1] = std::max(q[1], x);
+            q[2] = std::min(q[2], y);
+            q[3] = std::max(q[3], y);
+        }
+        q[4] = p[0];
+        q[5] = p[1];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], q[2 * a]);
+            hi[a] = std::max(hi[a], q[2 * a + 1]);
+        }
+        if (material[b] < -1) return fail(MT_ERR_INVALID_ARG, "material[%d] < -1", b);
+        mat[b] = material[b];
+        max_mat = std::max(max_mat, material[b]);
+        const int m = magnet ? magnet[b] : -1;
+        if (m < -1 || m >= n_mag)
+            return fail(MT_ERR_INVALID_ARG, "magnet[%d] = %d not in [-1, n_mag)", b, m);
+        mag[b] = m;
+        bf[b] = b_box ? make_float4(b_box[3 * b], b_box[3 * b + 1], b_box[3 * b + 2], 0.f)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // Grid: about kGridCells roughly cubic cells over the bounding box grown by
+    // a margin far above the rounding of a cell index.
+    double ext[3], eps = 0.0;
+    for (int a = 0; a < 3; ++a) eps = std::max(eps, hi[a] - lo[a]);
+    eps = 1e-6 * (1.0 + eps);
+    for (int a = 0; a < 3; ++a) {
+        lo[a] -= eps;
+        hi[a] += eps;
+        ext[a] = hi[a] - lo[a];
+    }
+    const double cell = std::cbrt(ext[0] * ext[1] * ext[2] / (double)mt::kGridCells);
+    int dims[3];
+    for (int a = 0; a < 3; ++a) dims[a] = (int)std::max(1.0, std::min(256.0, std::floor(ext[a] / cell)));
+    while ((int64_t)dims[0] * dims[1] * dims[2] > mt::kGridCells) {
+        int a = 0;
+        for (int c = 1; c < 3; ++c)
+            if (ext[c] / dims[c] < ext[a] / dims[a]) a = c;
+        --dims[a];
+    }
+    const int G = dims[0] * dims[1] * dims[2];
+    std::vector<uint64_t> grid((size_t)G, 0ull);
+    for (int b = 0; b < n; ++b) {
+        const double *q = bb.data() + 6 * b;
+        int c0[3], c1[3];
+        for (int a = 0; a < 3; ++a) {
+            const double w = ext[a] / dims[a];
+            c0[a] = std::max(0, (int)std::floor((q[2 * a] - eps - lo[a]) / w));
+            c1[a] = std::min(dims[a] - 1, (int)std::floor((q[2 * a + 1] + eps - lo[a]) / w));
+        }
+        for (int k = c0[2]; k <= c1[2]; ++k)
+            for (int j = c0[1]; j <= c1[1]; ++j)
+                for (int i = c0[0]; i <= c1[0]; ++i)
+                    grid[((size_t)k * dims[1] + j) * dims[0] + i] |= 1ull << b;
+    }
+    if ((rc = ensure_device())) return rc;
+    if ((rc = g.blk.upload(rec.data(), rec.size() * 8))) return rc;
+    if ((rc = g.grid.upload(grid.data(), grid.size() * 8))) return rc;
+    if ((rc = g.bfield.upload(bf.data(), bf.size() * 16))) return rc;
+    if ((rc = g.material.upload(mat.data(), mat.size() * 4))) return rc;
+    if ((rc = g.magnet.upload(mag.data(), mag.size() * 4))) return rc;
+    mt::DevGeom &G_ = g.T.geom;
+    G_.n_box = n;
+    G_.n_poly = n;
+    G_.n_slab = 0;
+    G_.n_mag = n_mag;
+    G_.disjoint = 0;
+    G_.box4 = nullptr;
+    G_.slab_z = nullptr;
+    G_.slab_mask = nullptr;
+    G_.poly = reinterpret_cast<const double *>(g.blk.p);
+    G_.grid = reinterpret_cast<const uint64_t *>(g.grid.p);
+    G_.gx = dims[0];
+    G_.gy = dims[1];
+    G_.gz = dims[2];
+    for (int a = 0; a < 3; ++a) {
+        G_.g0[a] = lo[a];
+        G_.ginv[a] = (double)dims[a] / ext[a];
+    }
+    G_.material = reinterpret_cast<const int32_t *>(g.material.p);
+    G_.bfield = reinterpret_cast<const float4 *>(g.bfield.p);
+    G_.magnet = reinterpret_cast<const int32_t *>(g.magnet.p);
+    G_.x_max = world[0];
+    G_.y_max = world[1];
+    G_.z_max = world[2];
     g.max_material = max_mat;
     g.geom_loaded = true;
     relayout();
@@ -765,7 +934,7 @@ const char *mt_last_error(void) { return g_err.c_str(); }
 void mt_release(void) {
     std::lock_guard<std::mutex> lk(g.mu);
     drop_graphs();
-    for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.alias, &g.box4, &g.material, &g.bfield,
+    for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.alias, &g.blk, &g.grid, &g.box4, &g.material, &g.bfield,
                       &g.magnet, &g.slab_z, &g.slab_mask, &g.map, &g.queue, &g.partial,
                       &g.scratch, &g.gs_lane, &g.zero_dummy})
         b->release();

@@ -12,6 +12,8 @@ namespace mt {
 constexpr int kWave = 64;
 constexpr int kCkptEvery = 16;             // RK4 state checkpoint interval
 constexpr double kKappa = 0.299792458;     // GeV / (c T m)
+constexpr int kBlockRec = 20;              // doubles per convex block record
+constexpr int kGridCells = 1024;           // cells of the block grid (LDS-resident)
 
 // Histogram tables on the device.  cdf[h][c] is the inclusive cumulative
 // count of cell c of histogram h = material * n_pbin + bin; guide[h][g]
@@ -33,7 +35,12 @@ struct DevHist {
 // when box b spans the whole slab in z, so inside the slab only the x and y
 // ranges of those boxes need testing, lowest index first.
 struct DevGeom {
-    int32_t n_box, n_slab, n_mag;
+    int32_t n_box, n_slab, n_mag;    // n_box: volumes (boxes or blocks)
+    int32_t n_poly;              // > 0: the volumes are convex blocks
+    const double *poly;          // [n_poly][kBlockRec]
+    const uint64_t *grid;        // [gz][gy][gx] candidate masks of the block grid
+    int32_t gx, gy, gz;
+    double g0[3], ginv[3];       // grid origin and cells per metre
     int32_t disjoint;            // no two boxes overlap: a box that holds a point is its box
     const double *box4;          // [n_box][4] xlo, xhi, ylo, yhi
     const int32_t *material;     // [n_box]
@@ -54,6 +61,7 @@ struct DevField {
 // Byte offsets of the tables staged in LDS by every block.
 struct LdsLayout {
     int32_t off_e2, off_tot, off_box4, off_mat, off_bf, off_mag, off_slabz, off_slabm;
+    int32_t off_blk, off_grid;
     int32_t bytes;
 };
 

@@ -102,8 +102,11 @@ struct Lds {
     const int32_t *mag;
     const double *slabz;
     const uint64_t *slabm;
+    const double *blk;          // convex blocks [n_poly][kBlockRec]
+    const uint64_t *grid;       // block grid candidate masks
 };
 
+template <bool POLY>
 __device__ __forceinline__ Lds stage_tables(char *smem, const Tables &T) {
     const LdsLayout &L = T.lds;
     double *e2 = reinterpret_cast<double *>(smem + L.off_e2);
@@ -118,16 +121,24 @@ __device__ __forceinline__ Lds stage_tables(char *smem, const Tables &T) {
     for (int i = tid; i <= T.hist.n_pbin; i += nt) e2[i] = T.hist.edges2[i];
     const int nh = T.hist.n_mat * T.hist.n_pbin;
     for (int i = tid; i < nh; i += nt) tot[i] = T.hist.totals[i];
-    for (int i = tid; i < 4 * T.geom.n_box; i += nt) box4[i] = T.geom.box4[i];
     for (int i = tid; i < T.geom.n_box; i += nt) {
         mat[i] = T.geom.material[i];
         bf[i] = T.geom.bfield[i];
         mag[i] = T.geom.magnet[i];
     }
-    for (int i = tid; i <= T.geom.n_slab; i += nt) slabz[i] = T.geom.slab_z[i];
-    for (int i = tid; i < T.geom.n_slab; i += nt) slabm[i] = T.geom.slab_mask[i];
+    double *blk = reinterpret_cast<double *>(smem + L.off_blk);
+    uint64_t *grid = reinterpret_cast<uint64_t *>(smem + L.off_grid);
+    if constexpr (POLY) {
+        for (int i = tid; i < kBlockRec * T.geom.n_poly; i += nt) blk[i] = T.geom.poly[i];
+        const int G = T.geom.gx * T.geom.gy * T.geom.gz;
+        for (int i = tid; i < G; i += nt) grid[i] = T.geom.grid[i];
+    } else {
+        for (int i = tid; i < 4 * T.geom.n_box; i += nt) box4[i] = T.geom.box4[i];
+        for (int i = tid; i <= T.geom.n_slab; i += nt) slabz[i] = T.geom.slab_z[i];
+        for (int i = tid; i < T.geom.n_slab; i += nt) slabm[i] = T.geom.slab_mask[i];
+    }
     __syncthreads();
-    return Lds{e2, tot, box4, mat, bf, mag, slabz, slabm};
+    return Lds{e2, tot, box4, mat, bf, mag, slabz, slabm, blk, grid};
 }
 
 // ---------------------------------------------------------------------------
@@ -230,6 +241,53 @@ __device__ __forceinline__ int locate(Lane &L, const Tables &T, const Lds &S) {
     }
     L.vol = find_box(S, L.slab, L.x, L.y);
     return L.vol;
+}
+
+// Convex block b holds (x, y, z): z_lo <= z < z_hi and the edge cross
+// products of the slice at z (Eq. (1)) all >= 0 or all <= 0.
+__device__ __forceinline__ bool in_block(const Lds &S, int b, double x, double y, double z) {
+    const double *r = S.blk + kBlockRec * b;
+    if (!(r[0] <= z && z < r[1])) return false;
+    const double t = (z - r[0]) * r[2];
+    double vx[4], vy[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        vx[i] = fma(t, r[12 + 2 * i], r[4 + 2 * i]);
+        vy[i] = fma(t, r[13 + 2 * i], r[5 + 2 * i]);
+    }
+    bool pos = true, neg = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        const double si = (vx[j] - vx[i]) * (y - vy[i]) - (vy[j] - vy[i]) * (x - vx[i]);
+        pos = pos && si >= 0.0;
+        neg = neg && si <= 0.0;
+    }
+    return pos || neg;
+}
+
+// Lowest-index block holding the lane's position: the grid cell's candidate
+// mask, then the sign test, lowest index first.
+__device__ __forceinline__ int locate_block(Lane &L, const Tables &T, const Lds &S) {
+    const DevGeom &G = T.geom;
+    const double u = (L.x - G.g0[0]) * G.ginv[0];
+    const double v = (L.y - G.g0[1]) * G.ginv[1];
+    const double w = (L.z - G.g0[2]) * G.ginv[2];
+    int vol = -1;
+    if (u >= 0.0 && v >= 0.0 && w >= 0.0 && u < (double)G.gx && v < (double)G.gy &&
+        w < (double)G.gz) {
+        uint64_t m = S.grid[((int)w * G.gy + (int)v) * G.gx + (int)u];
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            if (in_block(S, b, L.x, L.y, L.z)) {
+                vol = b;
+                break;
+            }
+            m &= m - 1;
+        }
+    }
+    L.vol = vol;
+    return vol;
 }
 
 // Momentum bin i with e_i^2 <= |p|^2 < e_{i+1}^2, clamped to [0, P-1]; the
@@ -496,14 +554,16 @@ enum : unsigned {
     kAlias = 8u,     // alias-method sampler instead of the inverse CDF
     kNearest = 16u,  // nearest-node map lookup instead of trilinear (with kMap)
     kStages = 32u,   // field evaluated at every RK4 stage position
-    kFeatures = 64u  // number of masks
+    kPoly = 64u,     // convex-block geometry instead of boxes
+    kFeatures = 128u // number of masks
 };
 
 // Masks that have a kernel: the tape belongs to the differentiable form,
 // whose adjoint holds the trilinear field over each step, and the
 // nearest-node lookup needs a map.
 constexpr bool valid_mask(unsigned F) {
-    return !((F & kTape) && (F & (kNearest | kStages))) && !((F & kNearest) && !(F & kMap));
+    return !((F & kTape) && (F & (kNearest | kStages))) && !((F & kNearest) && !(F & kMap)) &&
+           !((F & kPoly) && (F & (kTape | kStages)));
 }
 
 // Map part of the field at a point.
@@ -578,7 +638,9 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
     st = (fabs(L.x) >= T.geom.x_max) ? MT_ST_XMAX : st;
     st = (L.z >= T.geom.z_max) ? MT_ST_ZMAX : st;
     st = (p2 < R.pmin2) ? MT_ST_PMIN : st;
-    const int vol = locate(L, T, S);
+    int vol;
+    if constexpr ((F & kPoly) != 0) vol = locate_block(L, T, S);
+    else vol = locate(L, T, S);
     if (st != MT_ST_RUNNING) {       // the muon stops here; vol is its final volume
         L.status = st;
         return false;
@@ -671,7 +733,7 @@ template <unsigned F>
 __global__ void __launch_bounds__(1024) k_plain(Tables T, DevRun R, DevIO io) {
     constexpr bool CKPT = (F & kTape) != 0;
     extern __shared__ __align__(16) char smem[];
-    const Lds S = stage_tables(smem, T);
+    const Lds S = stage_tables<(F & kPoly) != 0>(smem, T);
     const StepConst sc = step_const(R);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= R.lanes) return;
@@ -750,7 +812,7 @@ __global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO i
     extern __shared__ __align__(16) char smem[];
     __shared__ unsigned long long batch_base;
     __shared__ int wave_count[1024 / kWave];
-    const Lds S = stage_tables(smem, T);
+    const Lds S = stage_tables<(F & kPoly) != 0>(smem, T);
     MoveRec *recs = reinterpret_cast<MoveRec *>(smem + ((T.lds.bytes + 15) & ~15));
     const StepConst sc = step_const(R);
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
@@ -980,7 +1042,7 @@ template <bool MAP, bool LDSH>
 __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
                                                  double *g_in, double *gs_lane, char *scratch) {
     extern __shared__ __align__(16) char smem[];
-    const Lds S = stage_tables(smem, T);
+    const Lds S = stage_tables<false>(smem, T);
     const StepConst sc = step_const(R);
     const int bd = blockDim.x;
     const int n_mag = T.geom.n_mag;
@@ -1200,7 +1262,7 @@ static unsigned feature_mask(const Tables &T, const DevRun &R) {
     return (map ? kMap : 0u) | (R.ckpt != nullptr ? kTape : 0u) |
            (R.n_trace > 0 ? kTrace : 0u) | (R.sampler == MT_SAMPLER_ALIAS ? kAlias : 0u) |
            (map && R.interp == MT_INTERP_NEAREST ? kNearest : 0u) |
-           (R.stage_field ? kStages : 0u);
+           (R.stage_field ? kStages : 0u) | (T.geom.n_poly > 0 ? kPoly : 0u);
 }
 
 hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,

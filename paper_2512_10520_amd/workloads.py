@@ -22,6 +22,10 @@ here is a seeded stand-in with the shapes of the five workloads:
             all variants.
 ``diff``    ``scan`` geometry at unit scales with the 10^6 ``block`` muons;
             used for the differentiable (adjoint) form.
+``blocks``  the ``shield`` stations as 40 convex blocks: yokes and air core
+            taper along z (seeded per station), the walls stay prisms;
+            uniform per-block fields (yokes +-B_m along y, one magnet per
+            station), the ``shield`` histograms, 10^6 power-law muons.
 
 Every random draw comes from ``np.random.default_rng([2512, 10520, cfg,
 part, ...])`` with its own stream per array, so a prefix of the muon list is
@@ -36,8 +40,8 @@ from typing import Optional
 import numpy as np
 from scipy import special
 
-CONFIGS = ("tiny", "block", "shield", "scan", "diff")
-_CFG_CODE = {"tiny": 1, "block": 2, "shield": 3, "scan": 4, "diff": 5}
+CONFIGS = ("tiny", "block", "shield", "scan", "diff", "blocks")
+_CFG_CODE = {"tiny": 1, "block": 2, "shield": 3, "scan": 4, "diff": 5, "blocks": 6}
 
 # Part codes of the seed sequence.
 _PART_HIST, _PART_MUONS, _PART_GEOM, _PART_FIELD, _PART_VARIANTS = 0, 1, 2, 3, 4
@@ -298,6 +302,49 @@ def _shield(cfg_code: int):
     return geom, FieldMap(lo=lo, hi=hi, b=b)
 
 
+def _quad(x0, x1, y0, y1):
+    """Rectangle as a counter-clockwise quadrilateral [(x, y)] x 4."""
+    return [x0, y0, x1, y0, x1, y1, x0, y1]
+
+
+def _blocks(cfg_code: int) -> Geometry:
+    """The shield stations as convex blocks: at the exit of station m the air
+    core narrows by 2 s_m in x and the yokes follow it inwards and shrink by
+    s_m / 2 in y (s_m ~ U(0, 0.15) m); the concrete walls stay prisms.  Yoke
+    fields are uniform, (0, +-P_m B_m, 0) T, scaled by magnet m."""
+    rng_g = _rng(cfg_code, _PART_GEOM)
+    lengths = rng_g.uniform(2.0, 3.0, size=8)
+    polarity = rng_g.choice([-1.0, 1.0], size=8)
+    bmag = rng_g.uniform(1.5, 1.8, size=8)
+    taper = rng_g.uniform(0.0, 0.15, size=8)
+    blocks, mats, magnets, fields = [], [], [], []
+    z = 0.5
+    for m in range(8):
+        z0, z1, s = z, z + lengths[m], taper[m]
+        b = polarity[m] * bmag[m]
+        layout = (
+            (_quad(-1.2, -0.2, -1.0, 1.0), _quad(-1.2, -0.2 + s, -1.0 + s / 2, 1.0 - s / 2),
+             _IRON, m, -b),
+            (_quad(0.2, 1.2, -1.0, 1.0), _quad(0.2 - s, 1.2, -1.0 + s / 2, 1.0 - s / 2),
+             _IRON, m, b),
+            (_quad(-0.2, 0.2, -1.0, 1.0), _quad(-0.2 + s, 0.2 - s, -1.0, 1.0), _AIR, -1, 0.0),
+            (_quad(-2.0, -1.2, -2.0, 2.0), _quad(-2.0, -1.2, -2.0, 2.0), _CONCRETE, -1, 0.0),
+            (_quad(1.2, 2.0, -2.0, 2.0), _quad(1.2, 2.0, -2.0, 2.0), _CONCRETE, -1, 0.0),
+        )
+        for bottom, top, mat, mag, by in layout:
+            blocks.append([z0, z1] + bottom + top)
+            mats.append(mat)
+            magnets.append(mag)
+            fields.append((0.0, by, 0.0))
+        z = z1 + 0.5
+    n = len(blocks)
+    return Geometry(box=np.zeros((0, 6)), material=np.array(mats, dtype=np.int32),
+                    b_box=np.array(fields, dtype=np.float32),
+                    magnet=np.array(magnets, dtype=np.int32), n_mag=8,
+                    world=np.array([2.0, 2.0, 30.0], dtype=np.float64),
+                    poly=np.array(blocks, dtype=np.float64).reshape(n, 18))
+
+
 # --------------------------------------------------------------------------
 # Muons
 # --------------------------------------------------------------------------
@@ -380,7 +427,7 @@ class Workload:
 
 
 DEFAULT_MUONS = {"tiny": 10_000, "block": 1_000_000, "shield": 10_000_000,
-                 "scan": 1 << 17, "diff": 1_000_000}
+                 "scan": 1 << 17, "diff": 1_000_000, "blocks": 1_000_000}
 
 # Muons of the block-type workloads start a little before the first face; a
 # start at -0.0075 m keeps step starts off the faces at multiples of 0.625 m
@@ -412,6 +459,12 @@ def make_workload(name: str, n_muons: Optional[int] = None, n_fill: int = 1_000_
                                n_fill=n_fill)
         geom, fmap = _shield(3)
         return Workload(name, hist, geom, fmap, _power_law_muons(3, n, _Z0_BLOCK),
+                        RunParams(step=step, max_steps=2000, p_min=0.18, seed=0))
+    if name == "blocks":
+        # the shield's histograms (seeded as workload 3), blocks seeded as 6
+        hist = make_histograms(3, ("iron", "concrete", "air"), edges, 100, 100, step,
+                               n_fill=n_fill)
+        return Workload(name, hist, _blocks(6), None, _power_law_muons(6, n, _Z0_BLOCK),
                         RunParams(step=step, max_steps=2000, p_min=0.18, seed=0))
     # block, scan, diff share the block histograms (seeded as workload 2).
     hist = make_histograms(2, ("iron",), edges, 100, 100, step, n_fill=n_fill)

@@ -124,3 +124,21 @@ def test_geometry_and_field_validation(L):
     b = np.zeros((2, 2, 1, 3), np.float32)
     assert L.mt_load_field(1, 2, 2, lo.ctypes.data, hi.ctypes.data, b.ctypes.data) == -1
     assert L.mt_load_field(2, 2, 2, hi.ctypes.data, lo.ctypes.data, b.ctypes.data) == -1
+
+
+def test_block_geometry_validation(L):
+    world = np.array([1.0, 1.0, 1.0])
+    mat = np.array([0], np.int32)
+    sq = [0, 0, 1, 0, 1, 1, 0, 1]
+    good = np.array([[0.0, 1.0] + sq + sq], np.float64)
+    bad_z = np.array([[1.0, 1.0] + sq + sq], np.float64)
+    bowtie = np.array([[0.0, 1.0] + [0, 0, 1, 1, 1, 0, 0, 1] + sq], np.float64)
+    flipped = np.array([[0.0, 1.0] + sq + [0, 0, 0, 1, 1, 1, 1, 0]], np.float64)
+    for blk, msg in ((bad_z, "z_lo"), (bowtie, "convex"), (flipped, "convex")):
+        assert L.mt_load_blocks(1, blk.ctypes.data, mat.ctypes.data, None, None, 0,
+                                world.ctypes.data) == -1
+        assert msg in _err(L)
+    assert L.mt_load_blocks(0, good.ctypes.data, mat.ctypes.data, None, None, 0,
+                            world.ctypes.data) == -1
+    assert L.mt_load_blocks(65, good.ctypes.data, mat.ctypes.data, None, None, 0,
+                            world.ctypes.data) == -7

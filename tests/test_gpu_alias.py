@@ -35,9 +35,11 @@ def test_alias_tiny_full_parity_with_trace():
     s = compare(g, o, trace_rows=n, label="tiny alias")
     print("tiny alias", s)
     assert np.all(g["status"] == oracle.ST_ZMAX)
-    # the two samplers draw different cells from the same words
+    # the two samplers map the same words to different cells (at 100 GeV
+    # most of the mass sits in a few cells, so most draws still agree)
     c = gpu_run(W.make_workload("tiny"), trace_steps=64, n_trace=n)
-    assert (c["trace"][..., 2] != g["trace"][..., 2]).mean() > 0.5
+    mat = g["trace"][..., 0] >= 0
+    assert (c["trace"][..., 2] != g["trace"][..., 2])[mat].sum() > 1000
 
 
 @pytest.mark.parametrize("n", [65, 20_011])
