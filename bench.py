@@ -36,14 +36,18 @@ HBM_PEAK = 8.0e12
 # field 1, RK4 with FP64 accumulation 103, loop 2 -> 233 for a material step;
 # a vacuum step in zero field is 40.  The field map adds 30 (8 corner loads,
 # 21 lerps, index arithmetic); zero-field material steps replace the RK4 by
-# the straight-line update (-84).
-OPS = {"material": 233, "vacuum": 40, "map": 30, "straight": -84}
+# the straight-line update (-84).  A convex-block lookup replaces the box
+# lookup by one candidate's sign test (grid cell 9, slice 8 FMAs, 4 edge
+# products 24, sign logic 8: +43 over the cached box lookup).
+OPS = {"material": 233, "vacuum": 40, "map": 30, "straight": -84, "block_lookup": 43}
 
 WORKLOADS = {
     "tiny": "tiny: 1 iron box 1 m, no field, 32x64x64 histograms, 10^4 muons at 100 GeV",
     "block": "block: 5 m iron box, uniform 1.7 T, 95x100x100 histograms, 10^6 power-law muons",
     "shield": "shield: 40 boxes, 3 materials, 100x100x300 trilinear field map, 10^7 muons",
     "scan": "scan: 8 iron slabs, 64 field-scale variants x 2^17 muons, one graph launch",
+    "blocks": "blocks: 40 convex blocks (tapered yokes and core), 3 materials, 10^6 muons",
+    "logbins": "logbins: block with log10-binned histogram axes (the paper's parameterisation)",
 }
 
 
@@ -57,6 +61,10 @@ def _parse():
     ap.add_argument("--sampler", default="cdf", choices=["cdf", "alias"],
                     help="histogram-cell sampler of the timed pass (the other one is timed "
                          "beside it on the block workload)")
+    ap.add_argument("--interp", default="trilinear", choices=["trilinear", "nearest"],
+                    help="field map lookup (workloads with a map)")
+    ap.add_argument("--stage-field", action="store_true",
+                    help="evaluate the field at every RK4 stage position")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-design", action="store_true")
     ap.add_argument("--cpu-muons", type=int, default=1_000_000)
@@ -120,7 +128,8 @@ def main():
     use_graph = args.config == "scan"
 
     def spec_for(mode, sampler=args.sampler):
-        return api.RunSpec.from_workload(wl, mode=mode, sampler=sampler,
+        return api.RunSpec.from_workload(wl, mode=mode, sampler=sampler, interp=args.interp,
+                                         stage_field=args.stage_field,
                                          use_graph=use_graph and mode == "persistent")
 
     modes = ["plain", "persistent"] if args.mode == "auto" else [args.mode]
@@ -159,14 +168,15 @@ def main():
             "data": "synthetic",
             "config": {"workload": WORKLOADS[args.config], "muons": len(dm),
                        "lanes": int(out.n_steps.numel()), "muon_steps_per_pass": steps_per_pass,
-                       "mode": mode, "sampler": args.sampler, "mode_probe_ms": probe,
+                       "mode": mode, "sampler": args.sampler, "interp": args.interp,
+                       "stage_field": args.stage_field, "mode_probe_ms": probe,
                        "autotune": tuned},
             "roofline": roofline}
 
     if args.config == "scan":
         line["config"]["per_variant_plain_ms"] = per_variant_plain(api, dm, wl, scales, torch)
 
-    if args.config in ("block", "shield"):
+    if args.config in ("block", "shield", "blocks", "logbins"):
         other = "alias" if args.sampler == "cdf" else "cdf"
         so = spec_for(mode, other)
         oo = api.alloc_result(so, len(dm), "cuda")
@@ -211,10 +221,12 @@ def algorithmic_ops(config, steps, lanes):
     first step of every muon starts in vacuum before the box; tiny: zero
     field; shield: every step is counted as a material step with a map
     lookup (an upper bound: the air gaps are vacuum)."""
-    if config in ("block", "scan", "diff"):
+    if config in ("block", "scan", "diff", "logbins"):
         return (steps - lanes) * OPS["material"] + lanes * OPS["vacuum"]
     if config == "tiny":
         return (steps - lanes) * (OPS["material"] + OPS["straight"]) + lanes * OPS["vacuum"]
+    if config == "blocks":
+        return steps * (OPS["material"] + OPS["block_lookup"])
     return steps * (OPS["material"] + OPS["map"])
 
 

@@ -101,6 +101,37 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges,
                        int32_t n_scat, double scat_lo, double scat_hi,
                        const uint32_t *counts);
 
+/* Axis flags of mt_load_histograms_ex. */
+#define MT_AXIS_LOG_LOSS    1    /* loss bins uniform in log10 f over [loss_lo, loss_hi] */
+#define MT_AXIS_LOG_SCAT    2    /* kick bins uniform in log10 tau over [scat_lo, scat_hi] */
+
+/*
+ * mt_load_histograms with logarithmic axes (Section "Building histograms":
+ * log(-dPz/|P|) and log(dPt/|P|)).  On a log axis the bounds must be > 0,
+ * bin a covers [lo (hi/lo)^(a/n), lo (hi/lo)^((a+1)/n)), and the jitter of a
+ * drawn cell is uniform in log10 of the value.  axes = 0 is mt_load_histograms.
+ */
+int mt_load_histograms_ex(int32_t n_mat, int32_t n_pbin, const double *p_edges,
+                          int32_t n_loss, double loss_lo, double loss_hi,
+                          int32_t n_scat, double scat_lo, double scat_hi,
+                          const uint32_t *counts, int32_t axes);
+
+/*
+ * Optimal momentum binning by bounded variation (appendix "Optimal Momentum
+ * Binning"), a host computation: given an estimator phi (e.g. the pilot mean
+ * of log10 of the fractional loss) at n_probe ascending probe momenta, the
+ * edges start at p_probe[0]; after edge p_a the next edge is the first probe
+ * whose phi differs from phi(p_a) by more than eps (the supremum of the bins
+ * [p_a, p) whose probes all stay within eps), or the last probe.
+ *
+ *   edges     host double [max_edges] receives p_0 < ... < p_N
+ *   n_edges   receives N + 1
+ * Errors: MT_ERR_INVALID_ARG (n_probe < 2, unsorted probes, non-finite values,
+ *         eps < 0), MT_ERR_LIMIT (more than max_edges edges).
+ */
+int mt_optimal_edges(const double *p_probe, const double *phi, int32_t n_probe, double eps,
+                     double *edges, int32_t max_edges, int32_t *n_edges);
+
 /*
  * Geometry (Section "Simulation", item 1, specialised to axis-aligned boxes).
  *

@@ -60,6 +60,7 @@ class _Problem(C.Structure):
         ("seed", C.c_uint64),
         ("scales", C.c_void_p),
         ("sampler", C.c_int32),
+        ("log_loss", C.c_int32), ("log_scat", C.c_int32),
         ("interp", C.c_int32),
         ("stage_field", C.c_int32),
     ]
@@ -162,6 +163,8 @@ class Problem:
         sc = r.scales if scales is None else scales
         P.scales = None if sc is None else _ptr(keep(sc, np.float64))
         P.sampler = int(getattr(r, "sampler", 0))
+        la = getattr(h, "log_axes", (False, False))
+        P.log_loss, P.log_scat = int(bool(la[0])), int(bool(la[1]))
         P.interp = int(getattr(r, "interp", 0))
         P.stage_field = int(getattr(r, "stage_field", 0))
         self.struct = P
@@ -321,6 +324,34 @@ def nearest(wl, r) -> np.ndarray:
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+# --------------------------------------------------------------------------
+# Optimal momentum binning (appendix "Optimal Momentum Binning")
+# --------------------------------------------------------------------------
+def optimal_edges(p_probe, phi, eps):
+    """Bounded-variation momentum binning on a grid of probe momenta.
+
+    The variation of a candidate bin [p_a, p] is the largest |phi(p') -
+    phi(p_a)| over the probes p' in [p_a, p]; the next edge after p_a is the
+    supremum of the p for which it stays within eps.  On the probe grid that
+    supremum is the first probe whose estimate differs from phi(p_a) by more
+    than eps (every p below it passes, it fails), or the last probe.
+    Returns the edges p_0 = p_probe[0] < ... < p_N = p_probe[-1].
+    """
+    p = np.asarray(p_probe, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    edges = [p[0]]
+    a = 0
+    while a < len(p) - 1:
+        nxt = len(p) - 1
+        for j in range(a + 1, len(p)):
+            if abs(phi[j] - phi[a]) > eps:
+                nxt = j
+                break
+        edges.append(p[nxt])
+        a = nxt
+    return np.array(edges)
 
 
 # --------------------------------------------------------------------------

@@ -18,7 +18,9 @@
  *     from the cell word and its threshold from the low bytes of the other
  *     three words;
  *   - jitter: uniform within the drawn cell on both axes (Section
- *     "Simulation", item 2);
+ *     "Simulation", item 2); on an axis binned in log10 (the parameterisation
+ *     of Section "Building histograms") the jitter is uniform in log10 and the
+ *     value is 10 to that power;
  *   - kick: dp_local = |p| (tau cos phi, tau sin phi, -f), rotated into the
  *     global frame with the Rodrigues formula of Eq. (2), axis k = z x p_hat
  *     normalised and theta the angle between z and p_hat;
@@ -86,6 +88,7 @@ typedef struct {
     uint64_t seed;
     const double *scales;           /* [n_variants][n_mag] or NULL (all 1) */
     int32_t sampler;                /* 0 inverse CDF, 1 alias method */
+    int32_t log_loss, log_scat;     /* axis binned uniformly in log10 of the value */
     int32_t interp;                 /* map lookup: 0 trilinear, 1 nearest node */
     int32_t stage_field;            /* 0 B held from the step start, 1 B at every stage */
 } orc_problem;
@@ -564,8 +567,13 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
     double mpos = INFINITY, mp = INFINITY;
     const int64_t K = (int64_t)P->n_loss * P->n_scat;
     const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
-    const double wl = (P->loss_hi - P->loss_lo) / P->n_loss;
-    const double ws = (P->scat_hi - P->scat_lo) / P->n_scat;
+    /* axis origin and bin width, in log10 units on a logarithmic axis */
+    const double l0 = P->log_loss ? log10(P->loss_lo) : P->loss_lo;
+    const double l1 = P->log_loss ? log10(P->loss_hi) : P->loss_hi;
+    const double s0 = P->log_scat ? log10(P->scat_lo) : P->scat_lo;
+    const double s1 = P->log_scat ? log10(P->scat_hi) : P->scat_hi;
+    const double wl = (l1 - l0) / P->n_loss;
+    const double ws = (s1 - s0) / P->n_scat;
 
     double pm0 = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
     if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(pm0)) || pm0 == 0.0 ||
@@ -619,8 +627,10 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
                 cell = oracle_cdf_cell(C, K, t);
             }
             int64_t il = cell / P->n_scat, is = cell % P->n_scat;
-            double f = P->loss_lo + ((double)il + orc_unit(w[1])) * wl;
-            double tau = P->scat_lo + ((double)is + orc_unit(w[2])) * ws;
+            double f = l0 + ((double)il + orc_unit(w[1])) * wl;
+            double tau = s0 + ((double)is + orc_unit(w[2])) * ws;
+            if (P->log_loss) f = pow(10.0, f);
+            if (P->log_scat) tau = pow(10.0, tau);
             double phi = 2.0 * ORC_PI * orc_unit(w[3]);
             double dp[3] = {pm * tau * cos(phi), pm * tau * sin(phi), -pm * f};
             double pn[3];

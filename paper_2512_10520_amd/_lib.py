@@ -19,12 +19,13 @@ ERRORS = {-1: "MT_ERR_INVALID_ARG", -2: "MT_ERR_SHAPE", -3: "MT_ERR_EMPTY_HIST",
 MT_MODE_PLAIN, MT_MODE_PERSISTENT = 0, 1
 MT_SAMPLER_CDF, MT_SAMPLER_ALIAS = 0, 1
 MT_INTERP_TRILINEAR, MT_INTERP_NEAREST = 0, 1
+MT_AXIS_LOG_LOSS, MT_AXIS_LOG_SCAT = 1, 2
 ST_RUNNING, ST_PMIN, ST_ZMAX, ST_XMAX, ST_YMAX, ST_MAXSTEPS, ST_INVALID = range(7)
 CKPT_EVERY = 16
 
 # Names of every entry point the header declares (checked by the CPU tests).
-EXPORTS = ("mt_load_histograms", "mt_load_geometry", "mt_load_blocks", "mt_load_field",
-           "mt_propagate",
+EXPORTS = ("mt_load_histograms", "mt_load_histograms_ex", "mt_optimal_edges",
+           "mt_load_geometry", "mt_load_blocks", "mt_load_field", "mt_propagate",
            "mt_propagate_backward", "mt_autotune", "mt_last_error", "mt_release",
            "mt_device_info")
 
@@ -66,6 +67,9 @@ def load():
             L = C.CDLL(LIB_PATH)
             vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
             L.mt_load_histograms.argtypes = [i32, i32, vp, i32, dbl, dbl, i32, dbl, dbl, vp]
+            L.mt_load_histograms_ex.argtypes = [i32, i32, vp, i32, dbl, dbl, i32, dbl, dbl, vp,
+                                                i32]
+            L.mt_optimal_edges.argtypes = [vp, vp, i32, dbl, vp, i32, C.POINTER(i32)]
             L.mt_load_geometry.argtypes = [i32, vp, vp, vp, vp, i32, vp]
             L.mt_load_blocks.argtypes = [i32, vp, vp, vp, vp, i32, vp]
             L.mt_load_field.argtypes = [i32, i32, i32, vp, vp, vp]

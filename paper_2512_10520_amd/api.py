@@ -43,9 +43,24 @@ def load_histograms(hist) -> None:
     edges = _host(hist.p_edges, np.float64)
     counts = _host(hist.counts, np.uint32)
     n_mat, n_pbin, n_loss, n_scat = counts.shape
-    check(L.mt_load_histograms(n_mat, n_pbin, edges.ctypes.data, n_loss, float(hist.loss_lo),
-                               float(hist.loss_hi), n_scat, float(hist.scat_lo),
-                               float(hist.scat_hi), counts.ctypes.data))
+    la = getattr(hist, "log_axes", (False, False))
+    axes = (_lib.MT_AXIS_LOG_LOSS if la[0] else 0) | (_lib.MT_AXIS_LOG_SCAT if la[1] else 0)
+    check(L.mt_load_histograms_ex(n_mat, n_pbin, edges.ctypes.data, n_loss,
+                                  float(hist.loss_lo), float(hist.loss_hi), n_scat,
+                                  float(hist.scat_lo), float(hist.scat_hi), counts.ctypes.data,
+                                  axes))
+
+
+def optimal_edges(p_probe, phi, eps: float, max_edges: int = 4096) -> np.ndarray:
+    """Bounded-variation momentum binning (``mt_optimal_edges``, host code)."""
+    L = _lib.load()
+    p = _host(p_probe, np.float64)
+    f = _host(phi, np.float64)
+    out = np.zeros(max_edges, np.float64)
+    n = C.c_int32(0)
+    check(L.mt_optimal_edges(p.ctypes.data, f.ctypes.data, len(p), float(eps), out.ctypes.data,
+                             int(max_edges), C.byref(n)))
+    return out[:n.value].copy()
 
 
 _loaded = {"n_mag": 0}

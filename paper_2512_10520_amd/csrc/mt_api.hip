@@ -440,8 +440,52 @@ static void alias_table(const uint32_t *count, int64_t K, uint64_t T, uint2 *out
 int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int32_t n_loss,
                        double loss_lo, double loss_hi, int32_t n_scat, double scat_lo,
                        double scat_hi, const uint32_t *counts) {
+    return mt_load_histograms_ex(n_mat, n_pbin, p_edges, n_loss, loss_lo, loss_hi, n_scat,
+                                 scat_lo, scat_hi, counts, 0);
+}
+
+int mt_optimal_edges(const double *p_probe, const double *phi, int32_t n_probe, double eps,
+                     double *edges, int32_t max_edges, int32_t *n_edges) {
+    if (!p_probe || !phi || !edges || !n_edges)
+        return fail(MT_ERR_INVALID_ARG, "pointers must be non-NULL");
+    if (n_probe < 2) return fail(MT_ERR_INVALID_ARG, "need at least two probe momenta");
+    if (!(eps >= 0.0) || !std::isfinite(eps))
+        return fail(MT_ERR_INVALID_ARG, "eps must be finite and >= 0");
+    for (int32_t j = 0; j < n_probe; ++j) {
+        if (!std::isfinite(p_probe[j]) || !std::isfinite(phi[j]))
+            return fail(MT_ERR_INVALID_ARG, "probe %d: values must be finite", j);
+        if (j > 0 && !(p_probe[j] > p_probe[j - 1]))
+            return fail(MT_ERR_INVALID_ARG, "probe momenta must be strictly ascending");
+    }
+    int32_t count = 0;
+    auto put = [&](double v) {
+        if (count >= max_edges) return false;
+        edges[count++] = v;
+        return true;
+    };
+    if (!put(p_probe[0])) return fail(MT_ERR_LIMIT, "max_edges = %d is too small", max_edges);
+    int32_t start = 0;
+    while (start < n_probe - 1) {
+        const double ref = phi[start];
+        int32_t next = start + 1;
+        while (next < n_probe - 1 && std::fabs(phi[next] - ref) <= eps) ++next;
+        if (!put(p_probe[next])) return fail(MT_ERR_LIMIT, "max_edges = %d is too small", max_edges);
+        start = next;
+    }
+    *n_edges = count;
+    return MT_OK;
+}
+
+int mt_load_histograms_ex(int32_t n_mat, int32_t n_pbin, const double *p_edges, int32_t n_loss,
+                          double loss_lo, double loss_hi, int32_t n_scat, double scat_lo,
+                          double scat_hi, const uint32_t *counts, int32_t axes) {
     std::lock_guard<std::mutex> lk(g.mu);
     int rc = MT_OK;
+    if (axes & ~(MT_AXIS_LOG_LOSS | MT_AXIS_LOG_SCAT))
+        return fail(MT_ERR_INVALID_ARG, "unknown axis flags %d", axes);
+    const bool log_l = (axes & MT_AXIS_LOG_LOSS) != 0, log_s = (axes & MT_AXIS_LOG_SCAT) != 0;
+    if ((log_l && !(loss_lo > 0.0)) || (log_s && !(scat_lo > 0.0)))
+        return fail(MT_ERR_INVALID_ARG, "a logarithmic axis needs lo > 0");
     if (n_mat < 1 || n_pbin < 1 || n_loss < 1 || n_scat < 1)
         return fail(MT_ERR_INVALID_ARG, "n_mat, n_pbin, n_loss and n_scat must be >= 1");
     if (!p_edges || !counts) return fail(MT_ERR_INVALID_ARG, "p_edges and counts must be non-NULL");
@@ -471,7 +515,8 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
         if (v >= 1 && v <= 16) gbits = v;
     }
     const int64_t G = (int64_t)1 << gbits;
-    std::vector<uint32_t> cdf((size_t)(nh * K)), guide((size_t)(nh * G)), totals((size_t)nh);
+    std::vector<uint32_t> cdf((size_t)(nh * K)), totals((size_t)nh);
+    std::vector<uint2> guide((size_t)(nh * G));
     std::vector<uint2> alias((size_t)(nh * K));
     for (int64_t h = 0; h < nh; ++h) {
         uint64_t acc = 0;
@@ -492,13 +537,13 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
         auto cell_of = [&](uint32_t t) {
             return (uint32_t)(std::upper_bound(C, C + K, t) - C);
         };
-        uint32_t *Gd = guide.data() + h * G;
+        uint2 *Gd = guide.data() + h * G;
         for (int64_t gi = 0; gi < G; ++gi) {
             const uint64_t w_lo = (uint64_t)gi << (32 - gbits);
             const uint64_t w_hi = (((uint64_t)gi + 1) << (32 - gbits)) - 1;
             const uint32_t lo = cell_of((uint32_t)((w_lo * T) >> 32));
             const uint32_t hi = cell_of((uint32_t)((w_hi * T) >> 32));
-            Gd[gi] = lo | (hi << 16);
+            Gd[gi] = make_uint2(lo | (hi << 16), C[lo]);
         }
         alias_table(src, K, T, alias.data() + h * K);
     }
@@ -506,13 +551,13 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
     for (int i = 0; i <= n_pbin; ++i) e2[i] = p_edges[i] * p_edges[i];
     if ((rc = ensure_device())) return rc;
     if ((rc = g.cdf.upload(cdf.data(), cdf.size() * 4))) return rc;
-    if ((rc = g.guide.upload(guide.data(), guide.size() * 4))) return rc;
+    if ((rc = g.guide.upload(guide.data(), guide.size() * sizeof(uint2)))) return rc;
     if ((rc = g.totals.upload(totals.data(), totals.size() * 4))) return rc;
     if ((rc = g.edges2.upload(e2.data(), e2.size() * 8))) return rc;
     if ((rc = g.alias.upload(alias.data(), alias.size() * sizeof(uint2)))) return rc;
     mt::DevHist &H = g.T.hist;
     H.cdf = reinterpret_cast<const uint32_t *>(g.cdf.p);
-    H.guide = reinterpret_cast<const uint32_t *>(g.guide.p);
+    H.guide = reinterpret_cast<const uint2 *>(g.guide.p);
     H.totals = reinterpret_cast<const uint32_t *>(g.totals.p);
     H.edges2 = reinterpret_cast<const double *>(g.edges2.p);
     H.alias = reinterpret_cast<const uint2 *>(g.alias.p);
@@ -523,10 +568,15 @@ int mt_load_histograms(int32_t n_mat, int32_t n_pbin, const double *p_edges, int
     H.n_cells = (int32_t)K;
     H.gbits = gbits;
     H.nscat_magic = (uint32_t)((0x100000000ull / (uint64_t)n_scat) + 1);
-    H.loss_lo = (float)loss_lo;
-    H.loss_w = (float)((loss_hi - loss_lo) / n_loss);
-    H.scat_lo = (float)scat_lo;
-    H.scat_w = (float)((scat_hi - scat_lo) / n_scat);
+    // axis origin and bin width in the axis' own units (log10 on a log axis)
+    const double l0 = log_l ? std::log10(loss_lo) : loss_lo, l1 = log_l ? std::log10(loss_hi) : loss_hi;
+    const double s0 = log_s ? std::log10(scat_lo) : scat_lo, s1 = log_s ? std::log10(scat_hi) : scat_hi;
+    H.loss_lo = (float)l0;
+    H.loss_w = (float)((l1 - l0) / n_loss);
+    H.scat_lo = (float)s0;
+    H.scat_w = (float)((s1 - s0) / n_scat);
+    H.log_loss = log_l ? 1 : 0;
+    H.log_scat = log_s ? 1 : 0;
     g.n_mat = n_mat;
     g.n_pbin = n_pbin;
     g.hist_loaded = true;

@@ -18,16 +18,19 @@ constexpr int kGridCells = 1024;           // cells of the block grid (LDS-resid
 // Histogram tables on the device.  cdf[h][c] is the inclusive cumulative
 // count of cell c of histogram h = material * n_pbin + bin; guide[h][g]
 // brackets the answer of the inverse-CDF search for every word whose top
-// gbits bits equal g (low 16 bits: first candidate cell, high 16 bits: last).
+// gbits bits equal g: x = first candidate cell lo (low 16 bits) and last
+// candidate hi (high 16 bits), y = cdf[h][lo], so that any bucket spanning
+// at most two cells resolves without a probe of cdf.
 struct DevHist {
     const uint32_t *cdf;
-    const uint32_t *guide;       // nullptr: search the whole row
+    const uint2 *guide;          // [h][2^gbits]
     const uint32_t *totals;      // [n_hist]
     const double *edges2;        // [n_pbin + 1] squared momentum edges
     const uint2 *alias;          // [h][c] alias method: (24-bit threshold split, alias cell)
     int32_t n_mat, n_pbin, n_loss, n_scat, n_cells, gbits;
     uint32_t nscat_magic;        // floor(2^32 / n_scat) + 1 for exact c / n_scat, c < 2^16
-    float loss_lo, loss_w, scat_lo, scat_w;
+    float loss_lo, loss_w, scat_lo, scat_w;   // log10 units on a logarithmic axis
+    int32_t log_loss, log_scat;  // axis binned uniformly in log10 of the value
 };
 
 // Geometry: boxes split into z-slabs.  Slab s covers [slab_z[s], slab_z[s+1])

@@ -318,14 +318,17 @@ __device__ __forceinline__ int bin_of(Lane &L, const Tables &T, const Lds &S, do
 }
 
 // Exact inverse CDF: t = floor(w * T / 2^32), cell = smallest c with C[c] > t.
-// The guide entry of the word's top bits brackets c, so most draws need no
-// probe of C at all.
+// The guide entry of the word's top bits brackets c in [lo, hi] and carries
+// C[lo]: t < C[lo] gives lo at once, a bracket of two cells gives hi, and only
+// wider brackets probe C.
 __device__ __forceinline__ int sample_cell(const DevHist &H, const Lds &S, int h, uint32_t w0) {
     const uint32_t T = S.tot[h];
     const uint32_t t = __umulhi(w0, T);
-    const uint32_t pk = H.guide[((size_t)h << H.gbits) | (w0 >> (32 - H.gbits))];
-    int lo = (int)(pk & 0xFFFFu);
-    int hi = (int)(pk >> 16);
+    const uint2 e = H.guide[((size_t)h << H.gbits) | (w0 >> (32 - H.gbits))];
+    int lo = (int)(e.x & 0xFFFFu);
+    int hi = (int)(e.x >> 16);
+    if (t < e.y) return lo;
+    ++lo;
     const uint32_t *C = H.cdf + (size_t)h * H.n_cells;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -555,7 +558,8 @@ enum : unsigned {
     kNearest = 16u,  // nearest-node map lookup instead of trilinear (with kMap)
     kStages = 32u,   // field evaluated at every RK4 stage position
     kPoly = 64u,     // convex-block geometry instead of boxes
-    kFeatures = 128u // number of masks
+    kLog = 128u,     // a histogram axis is binned in log10
+    kFeatures = 256u // number of masks
 };
 
 // Masks that have a kernel: the tape belongs to the differentiable form,
@@ -659,8 +663,12 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         const float v1 = (float)(w.y >> 8) * 0x1p-24f;
         const float v2 = (float)(w.z >> 8) * 0x1p-24f;
         const float v3 = (float)(w.w >> 8) * 0x1p-24f;
-        const float f = fmaf((float)il + v1, T.hist.loss_w, T.hist.loss_lo);
-        const float tau = fmaf((float)is + v2, T.hist.scat_w, T.hist.scat_lo);
+        float f = fmaf((float)il + v1, T.hist.loss_w, T.hist.loss_lo);
+        float tau = fmaf((float)is + v2, T.hist.scat_w, T.hist.scat_lo);
+        if constexpr ((F & kLog) != 0) {      // jitter uniform in log10 of the value
+            if (T.hist.log_loss) f = exp10f(f);
+            if (T.hist.log_scat) tau = exp10f(tau);
+        }
         // v_sin_f32 / v_cos_f32 take their argument in revolutions: sin(2 pi v3).
         const float sn = __builtin_amdgcn_sinf(v3);
         const float cs = __builtin_amdgcn_cosf(v3);
@@ -1262,7 +1270,8 @@ static unsigned feature_mask(const Tables &T, const DevRun &R) {
     return (map ? kMap : 0u) | (R.ckpt != nullptr ? kTape : 0u) |
            (R.n_trace > 0 ? kTrace : 0u) | (R.sampler == MT_SAMPLER_ALIAS ? kAlias : 0u) |
            (map && R.interp == MT_INTERP_NEAREST ? kNearest : 0u) |
-           (R.stage_field ? kStages : 0u) | (T.geom.n_poly > 0 ? kPoly : 0u);
+           (R.stage_field ? kStages : 0u) | (T.geom.n_poly > 0 ? kPoly : 0u) |
+           (T.hist.log_loss || T.hist.log_scat ? kLog : 0u);
 }
 
 hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,

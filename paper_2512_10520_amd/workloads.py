@@ -22,6 +22,9 @@ here is a seeded stand-in with the shapes of the five workloads:
             all variants.
 ``diff``    ``scan`` geometry at unit scales with the 10^6 ``block`` muons;
             used for the differentiable (adjoint) form.
+``logbins`` ``block`` geometry and muons with the paper's histogram
+            parameterisation: both axes binned in log10 (f in [1e-6, 1],
+            tau in [1e-6, 0.5]), 95 log momentum bins.
 ``blocks``  the ``shield`` stations as 40 convex blocks: yokes and air core
             taper along z (seeded per station), the walls stay prisms;
             uniform per-block fields (yokes +-B_m along y, one magnet per
@@ -40,8 +43,9 @@ from typing import Optional
 import numpy as np
 from scipy import special
 
-CONFIGS = ("tiny", "block", "shield", "scan", "diff", "blocks")
-_CFG_CODE = {"tiny": 1, "block": 2, "shield": 3, "scan": 4, "diff": 5, "blocks": 6}
+CONFIGS = ("tiny", "block", "shield", "scan", "diff", "blocks", "logbins")
+_CFG_CODE = {"tiny": 1, "block": 2, "shield": 3, "scan": 4, "diff": 5, "blocks": 6,
+             "logbins": 7}
 
 # Part codes of the seed sequence.
 _PART_HIST, _PART_MUONS, _PART_GEOM, _PART_FIELD, _PART_VARIANTS = 0, 1, 2, 3, 4
@@ -67,8 +71,10 @@ class Histograms:
     """Count histograms H[M][i] over (fractional loss f, transverse kick tau).
 
     ``counts[m, i, a, b]`` counts muons of material ``m`` and momentum bin ``i``
-    whose loss fell in linear bin ``a`` of [loss_lo, loss_hi] and whose kick
-    fell in linear bin ``b`` of [scat_lo, scat_hi].  ``p_edges`` are the
+    whose loss fell in bin ``a`` of [loss_lo, loss_hi] and whose kick fell in
+    bin ``b`` of [scat_lo, scat_hi].  Bins are uniform in the value, or in its
+    base-10 logarithm on an axis marked in ``log_axes`` (loss, kick), the
+    parameterisation of Section "Building histograms".  ``p_edges`` are the
     momentum-bin edges e_0 < ... < e_P in GeV/c.
     """
 
@@ -79,6 +85,7 @@ class Histograms:
     scat_hi: float
     counts: np.ndarray           # uint32 [M][P][nL][nS]
     material_names: tuple = ()
+    log_axes: tuple = (False, False)
 
     @property
     def n_mat(self) -> int:
@@ -150,7 +157,7 @@ def _cell_probabilities(p_rep: float, a_m: float, x0: float, step: float,
 def make_histograms(cfg_code: int, materials: tuple, p_edges: np.ndarray,
                     n_loss: int, n_scat: int, step: float,
                     loss_range=(0.0, 0.05), scat_range=(0.0, 5e-3),
-                    n_fill: int = 1_000_000) -> Histograms:
+                    n_fill: int = 1_000_000, log_axes=(False, False)) -> Histograms:
     """Fill one count histogram per (material, momentum bin).
 
     Each histogram holds exactly ``n_fill`` in-range (loss, kick) pairs drawn
@@ -160,8 +167,9 @@ def make_histograms(cfg_code: int, materials: tuple, p_edges: np.ndarray,
     which is what is done here (seeded per material and bin).
     """
     n_mat, n_pbin = len(materials), len(p_edges) - 1
-    l_edges = np.linspace(loss_range[0], loss_range[1], n_loss + 1)
-    s_edges = np.linspace(scat_range[0], scat_range[1], n_scat + 1)
+    axis = lambda r, n, lg: np.geomspace(r[0], r[1], n + 1) if lg else np.linspace(r[0], r[1], n + 1)
+    l_edges = axis(loss_range, n_loss, log_axes[0])
+    s_edges = axis(scat_range, n_scat, log_axes[1])
     counts = np.empty((n_mat, n_pbin, n_loss, n_scat), dtype=np.uint32)
     for m, name in enumerate(materials):
         a_m, x0 = MATERIALS[name]
@@ -173,7 +181,23 @@ def make_histograms(cfg_code: int, materials: tuple, p_edges: np.ndarray,
     return Histograms(p_edges=np.asarray(p_edges, dtype=np.float64),
                       loss_lo=float(loss_range[0]), loss_hi=float(loss_range[1]),
                       scat_lo=float(scat_range[0]), scat_hi=float(scat_range[1]),
-                      counts=counts, material_names=tuple(materials))
+                      counts=counts, material_names=tuple(materials),
+                      log_axes=(bool(log_axes[0]), bool(log_axes[1])))
+
+
+def pilot_log_loss(material: str, p_probe: np.ndarray, step: float, k: int,
+                   cfg_code: int) -> np.ndarray:
+    """Pilot estimate of the mean log10 fractional loss at each probe momentum
+    (the estimator of the appendix "Optimal Momentum Binning"): ``k`` draws of
+    the loss recipe at each momentum, seeded per probe."""
+    a_m, _ = MATERIALS[material]
+    out = np.empty(len(p_probe))
+    for j, p in enumerate(p_probe):
+        mu = a_m * step / p
+        z = _rng(cfg_code, _PART_HIST, 99, j).standard_normal(k)
+        f = mu + 0.15 * mu * (-np.log(z * z))
+        out[j] = np.mean(np.log10(f[f > 0]))
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -427,7 +451,8 @@ class Workload:
 
 
 DEFAULT_MUONS = {"tiny": 10_000, "block": 1_000_000, "shield": 10_000_000,
-                 "scan": 1 << 17, "diff": 1_000_000, "blocks": 1_000_000}
+                 "scan": 1 << 17, "diff": 1_000_000, "blocks": 1_000_000,
+                 "logbins": 1_000_000}
 
 # Muons of the block-type workloads start a little before the first face; a
 # start at -0.0075 m keeps step starts off the faces at multiples of 0.625 m
@@ -466,6 +491,12 @@ def make_workload(name: str, n_muons: Optional[int] = None, n_fill: int = 1_000_
                                n_fill=n_fill)
         return Workload(name, hist, _blocks(6), None, _power_law_muons(6, n, _Z0_BLOCK),
                         RunParams(step=step, max_steps=2000, p_min=0.18, seed=0))
+    if name == "logbins":
+        hist = make_histograms(7, ("iron",), edges, 100, 100, step, loss_range=(1e-6, 1.0),
+                               scat_range=(1e-6, 0.5), n_fill=n_fill, log_axes=(True, True))
+        return Workload(name, hist, _single_box(5.0, 1.7), None,
+                        _power_law_muons(2, n, _Z0_BLOCK),
+                        RunParams(step=step, max_steps=1000, p_min=0.18, seed=0))
     # block, scan, diff share the block histograms (seeded as workload 2).
     hist = make_histograms(2, ("iron",), edges, 100, 100, step, n_fill=n_fill)
     if name == "block":

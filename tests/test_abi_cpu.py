@@ -142,3 +142,36 @@ def test_block_geometry_validation(L):
                             world.ctypes.data) == -1
     assert L.mt_load_blocks(65, good.ctypes.data, mat.ctypes.data, None, None, 0,
                             world.ctypes.data) == -7
+
+
+def test_optimal_edges_library_matches_oracle():
+    """mt_optimal_edges is host code: the library's binning equals the
+    oracle's on random estimators, tolerances and grids (edges are probe
+    momenta, so the comparison is exact)."""
+    import oracle
+    from paper_2512_10520_amd import api
+    rng = np.random.default_rng(17)
+    for _ in range(30):
+        m = int(rng.integers(2, 600))
+        p = np.sort(rng.uniform(0.1, 500.0, m))
+        p = np.unique(p)
+        phi = np.cumsum(rng.normal(0, rng.uniform(0.001, 0.3), len(p)))
+        eps = float(rng.choice([0.0, 0.01, 0.1, 1.0, 1e9]))
+        assert np.array_equal(api.optimal_edges(p, phi, eps), oracle.optimal_edges(p, phi, eps))
+
+
+def test_optimal_edges_validation(L):
+    p = np.array([1.0, 2.0, 3.0])
+    phi = np.zeros(3)
+    out = np.zeros(8)
+    n = C.c_int32(0)
+    assert L.mt_optimal_edges(p.ctypes.data, phi.ctypes.data, 3, -1.0, out.ctypes.data, 8,
+                              C.byref(n)) == -1
+    bad = np.array([1.0, 1.0, 3.0])
+    assert L.mt_optimal_edges(bad.ctypes.data, phi.ctypes.data, 3, 0.1, out.ctypes.data, 8,
+                              C.byref(n)) == -1
+    phi = np.array([0.0, 1.0, 2.0])
+    assert L.mt_optimal_edges(p.ctypes.data, phi.ctypes.data, 3, 0.1, out.ctypes.data, 2,
+                              C.byref(n)) == -7
+    assert L.mt_optimal_edges(p.ctypes.data, phi.ctypes.data, 3, 0.1, out.ctypes.data, 8,
+                              C.byref(n)) == 0 and n.value == 3

@@ -614,3 +614,59 @@ def test_overlapping_blocks_lowest_index():
     assert oracle.lookup(wl, [1.5, 1.5, 1.2]) == 1
     assert oracle.lookup(wl, [0.5, 0.5, 1.2]) == -1
     assert oracle.lookup(wl, [1.5, 1.5, 3.0]) == -1           # half-open in z
+
+
+# ------------------------------------------------------- optimal momentum binning
+def _check_bounded_variation(p, phi, eps, edges):
+    """Every bin [e_i, e_{i+1}) keeps its probes within eps of its first
+    probe, and (but for the last) cannot be extended: its upper edge is a probe
+    that differs by more than eps."""
+    idx = np.searchsorted(p, edges)
+    assert np.array_equal(p[idx], edges) and idx[0] == 0 and idx[-1] == len(p) - 1
+    assert np.all(np.diff(idx) > 0)
+    for a, b in zip(idx[:-1], idx[1:]):
+        assert np.all(np.abs(phi[a:b] - phi[a]) <= eps)
+        if b < len(p) - 1:
+            assert abs(phi[b] - phi[a]) > eps
+
+
+def test_optimal_edges_linear_estimator_closed_form():
+    """A linear estimator on a uniform grid (phi_j = -j delta) gives bins of
+    exactly floor(eps / delta) + 1 probes: the logarithmic binning of the paper
+    when the grid is logarithmic and phi linear in log p."""
+    M, delta, eps = 1001, 0.01, 0.0735
+    p = np.geomspace(0.18, 400.0, M)
+    phi = -delta * np.arange(M)
+    e = oracle.optimal_edges(p, phi, eps)
+    k = int(eps // delta) + 1
+    idx = np.searchsorted(p, e)
+    assert np.all(np.diff(idx)[:-1] == k) and 0 < np.diff(idx)[-1] <= k
+    assert len(e) - 1 == -(-(M - 1) // k)
+    ratios = e[1:-1] / e[:-2]
+    assert np.allclose(ratios, ratios[0], rtol=1e-12)            # log-uniform bins
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_optimal_edges_bounded_variation(seed):
+    rng = np.random.default_rng(seed)
+    p = np.sort(rng.uniform(0.1, 500.0, 400))
+    phi = np.cumsum(rng.normal(0, 0.05, 400)) + 3 * np.exp(-p / 20)
+    for eps in (0.02, 0.1, 0.5, 10.0):
+        e = oracle.optimal_edges(p, phi, eps)
+        _check_bounded_variation(p, phi, eps, e)
+    # a huge tolerance keeps one bin; a zero tolerance splits at every change
+    assert len(oracle.optimal_edges(p, phi, 1e9)) == 2
+    assert len(oracle.optimal_edges(p, phi, 0.0)) == len(p)
+
+
+def test_optimal_edges_on_the_pilot_estimator_narrow_at_low_momentum():
+    """On the pilot estimate of the mean log10 loss of the loss recipe (a
+    scale proportional to 1/p, so the estimator is linear in log p) the
+    binning bounds the variation and comes out close to equal widths in
+    log p: the logarithmic binning the paper settles on."""
+    p = np.geomspace(0.18, 400.0, 2001)
+    phi = W.pilot_log_loss("iron", p, 0.02, 4000, cfg_code=7)
+    e = oracle.optimal_edges(p, phi, 0.035)
+    _check_bounded_variation(p, phi, 0.035, e)
+    w = np.diff(np.log10(e))[:-1]
+    assert 60 < len(e) - 1 < 140 and w.std() / w.mean() < 0.5

@@ -36,8 +36,15 @@ def _one_step(hist, n, P=100.0, sampler=0):
 
 
 def _cells(hist, f, tau):
-    ul = (f - hist.loss_lo) / ((hist.loss_hi - hist.loss_lo) / hist.n_loss) + 1e-9
-    us = (tau - hist.scat_lo) / ((hist.scat_hi - hist.scat_lo) / hist.n_scat) + 1e-9
+    """Cell indices and position inside the cell (in the axis' own units:
+    log10 on a logarithmic axis) of recovered (f, tau) values."""
+    def axis(v, lo, hi, n, lg):
+        if lg:
+            v, lo, hi = np.log10(v), math.log10(lo), math.log10(hi)
+        return (v - lo) / ((hi - lo) / n) + 1e-9
+    la = getattr(hist, "log_axes", (False, False))
+    ul = axis(f, hist.loss_lo, hist.loss_hi, hist.n_loss, la[0])
+    us = axis(tau, hist.scat_lo, hist.scat_hi, hist.n_scat, la[1])
     il, is_ = np.floor(ul).astype(np.int64), np.floor(us).astype(np.int64)
     return il, is_, ul - il, us - is_
 
@@ -126,3 +133,29 @@ def test_log_momentum_moments_over_many_steps(sampler):
     assert abs(s.mean() - N * m1) < 5 * se, (s.mean(), N * m1, se)
     # steps draw independent words: the variance of the sum is N Var[g]
     assert abs(s.var() / (N * var_g) - 1) < 0.03
+
+
+@SAMPLERS
+def test_log_axes_cells_and_in_cell_uniformity(sampler):
+    """Histograms binned in log10 of f and tau (Section "Building
+    histograms"): the drawn cells follow the counts and the jitter is uniform
+    in log10 inside the cell (so f itself is not uniform in the cell)."""
+    rng = np.random.default_rng(31)
+    counts = rng.integers(0, 60, size=(8, 8)).astype(np.uint32)
+    counts[0, 3] = 0
+    hist = CU.flat_histograms(counts=counts, loss=(1e-4, 0.1), scat=(1e-5, 1e-2))
+    hist.log_axes = (True, True)
+    n = 600_000
+    f, tau, _ = _one_step(hist, n, sampler=sampler)
+    il, is_, fl, fs = _cells(hist, f, tau)
+    assert il.min() >= 0 and il.max() < 8 and is_.min() >= 0 and is_.max() < 8
+    obs = np.bincount(il * 8 + is_, minlength=64).astype(np.float64)
+    exp = n * counts.ravel() / counts.sum()
+    assert np.all(obs[counts.ravel() == 0] == 0)
+    assert _chi2_p(obs, exp) > 1e-4
+    assert stats.kstest(fl[:200_000], "uniform").pvalue > 1e-4
+    assert stats.kstest(fs[:200_000], "uniform").pvalue > 1e-4
+    # in linear units the position inside a loss cell is not uniform
+    lo = 10 ** (math.log10(1e-4) + il * (3.0 / 8))
+    hi = 10 ** (math.log10(1e-4) + (il + 1) * (3.0 / 8))
+    assert stats.kstest(((f - lo) / (hi - lo))[:200_000], "uniform").pvalue < 1e-6
