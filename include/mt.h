@@ -181,7 +181,11 @@ int mt_load_blocks(int32_t n, const double *block, const int32_t *material, cons
  * lo + (i, j, k) * (hi - lo) / (n - 1); outside [lo, hi] the map gives zero.
  *
  *   b   host float [nz][ny][nx][3] tesla; NULL unloads the map.
- * Requires nx, ny, nz >= 2 and lo < hi on every axis.
+ * Requires nx, ny, nz >= 2 and lo < hi on every axis.  The device holds a
+ * cell-major copy, the 8 corner values of each cell in one 128-byte record
+ * (128 (nx-1)(ny-1)(nz-1) bytes), so that a trilinear lookup reads one cache
+ * line, and a node-major copy (16 nx ny nz bytes) for the nearest node.
+ * Errors: MT_ERR_INVALID_ARG, MT_ERR_OOM, MT_ERR_HIP.
  */
 int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const double *hi,
                   const float *b);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <limits>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -85,7 +86,7 @@ struct State {
     bool hist_loaded = false, geom_loaded = false;
     int n_mat = 0, n_pbin = 0;
     int64_t version = 0;  // bumped on every table change
-    DevBuf cdf, guide, totals, edges2, alias, blk, grid;
+    DevBuf cdf, guide, totals, edges2, alias, blk, grid, nodes;
     DevBuf box4, material, bfield, magnet, slab_z, slab_mask;
     DevBuf map;
     DevBuf queue, partial, scratch, gs_lane, zero_dummy;
@@ -844,6 +845,7 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
     int rc = MT_OK;
     if (!b) {
         g.map.release();
+        g.nodes.release();
         g.T.field = mt::DevField{};
         tables_changed();
         return MT_OK;
@@ -853,13 +855,42 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] > lo[a]))
             return fail(MT_ERR_INVALID_ARG, "field bounds must be finite with hi > lo (axis %d)", a);
-    const size_t nodes = (size_t)nx * ny * nz;
-    std::vector<float4> m(nodes);
-    for (size_t i = 0; i < nodes; ++i) m[i] = make_float4(b[3 * i], b[3 * i + 1], b[3 * i + 2], 0.f);
+    // Cell-major copy: the 8 corner values of every cell in one 128-byte
+    // record (x fastest: c000 c100 c010 c110 c001 c101 c011 c111), so a
+    // lookup touches one cache line instead of four.
+    const size_t cx = (size_t)nx - 1, cy = (size_t)ny - 1, cz = (size_t)nz - 1;
+    const size_t cells = cx * cy * cz;
+    std::vector<float4> m;
+    try {
+        m.resize(cells * 8);
+    } catch (const std::bad_alloc &) {
+        return fail(MT_ERR_OOM, "host memory for %zu field-map cells", cells);
+    }
+    for (size_t k = 0; k < cz; ++k)
+        for (size_t j = 0; j < cy; ++j)
+            for (size_t i = 0; i < cx; ++i) {
+                float4 *rec = m.data() + ((k * cy + j) * cx + i) * 8;
+                for (int c = 0; c < 8; ++c) {
+                    const size_t node = ((k + (c >> 2)) * (size_t)ny + (j + ((c >> 1) & 1))) * nx +
+                                        (i + (c & 1));
+                    rec[c] = make_float4(b[3 * node], b[3 * node + 1], b[3 * node + 2], 0.f);
+                }
+            }
+    // Node-major copy for the nearest-node lookup (one value per lookup).
+    std::vector<float4> nd;
+    try {
+        nd.resize((size_t)nx * ny * nz);
+    } catch (const std::bad_alloc &) {
+        return fail(MT_ERR_OOM, "host memory for %zu field-map nodes", nd.size());
+    }
+    for (size_t i = 0; i < nd.size(); ++i)
+        nd[i] = make_float4(b[3 * i], b[3 * i + 1], b[3 * i + 2], 0.f);
     if ((rc = ensure_device())) return rc;
-    if ((rc = g.map.upload(m.data(), nodes * 16))) return rc;
+    if ((rc = g.map.upload(m.data(), m.size() * sizeof(float4)))) return rc;
+    if ((rc = g.nodes.upload(nd.data(), nd.size() * sizeof(float4)))) return rc;
     mt::DevField &F = g.T.field;
     F.map = reinterpret_cast<const float4 *>(g.map.p);
+    F.nodes = reinterpret_cast<const float4 *>(g.nodes.p);
     F.nx = nx;
     F.ny = ny;
     F.nz = nz;
@@ -984,7 +1015,7 @@ const char *mt_last_error(void) { return g_err.c_str(); }
 void mt_release(void) {
     std::lock_guard<std::mutex> lk(g.mu);
     drop_graphs();
-    for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.alias, &g.blk, &g.grid, &g.box4, &g.material, &g.bfield,
+    for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.alias, &g.blk, &g.grid, &g.nodes, &g.box4, &g.material, &g.bfield,
                       &g.magnet, &g.slab_z, &g.slab_mask, &g.map, &g.queue, &g.partial,
                       &g.scratch, &g.gs_lane, &g.zero_dummy})
         b->release();

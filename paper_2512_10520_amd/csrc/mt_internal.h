@@ -55,7 +55,9 @@ struct DevGeom {
 };
 
 struct DevField {
-    const float4 *map;           // [nz][ny][nx] (bx, by, bz, 0); nullptr = no map
+    const float4 *map;           // cell-major [nz-1][ny-1][nx-1][8 corners] (bx, by, bz, 0),
+                                 // corner c = (c & 1, c >> 1 & 1, c >> 2) offsets; nullptr = no map
+    const float4 *nodes;         // node-major [nz][ny][nx] (bx, by, bz, 0), for the nearest node
     int32_t nx, ny, nz;
     double lo[3];
     double inv_d[3];             // (n - 1) / (hi - lo)

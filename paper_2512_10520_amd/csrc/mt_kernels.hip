@@ -400,16 +400,15 @@ __device__ __forceinline__ bool map_cell(const DevField &F, double x, double y, 
     c.fx = (float)(u - (double)i);
     c.fy = (float)(v - (double)j);
     c.fz = (float)(w - (double)k);
-    const size_t sy = (size_t)F.nx, sz = (size_t)F.nx * F.ny;
-    const float4 *b = F.map + (size_t)k * sz + (size_t)j * sy + i;
+    const float4 *b = F.map + (((size_t)k * (F.ny - 1) + j) * (F.nx - 1) + i) * 8;
     c.c000 = b[0];
     c.c100 = b[1];
-    c.c010 = b[sy];
-    c.c110 = b[sy + 1];
-    c.c001 = b[sz];
-    c.c101 = b[sz + 1];
-    c.c011 = b[sz + sy];
-    c.c111 = b[sz + sy + 1];
+    c.c010 = b[2];
+    c.c110 = b[3];
+    c.c001 = b[4];
+    c.c101 = b[5];
+    c.c011 = b[6];
+    c.c111 = b[7];
     return true;
 }
 
@@ -460,7 +459,7 @@ __device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const 
 
 // Nearest-node lookup of the map: the node closest to (x, y, z) on every axis
 // (half-way points take the higher node), zero outside the grid.  One
-// 16-byte load.
+// 16-byte load from the node-major copy of the map.
 __device__ __forceinline__ float3 map_nearest(const DevField &F, double x, double y, double z) {
     const double u = (x - F.lo[0]) * F.inv_d[0];
     const double v = (y - F.lo[1]) * F.inv_d[1];
@@ -470,7 +469,7 @@ __device__ __forceinline__ float3 map_nearest(const DevField &F, double x, doubl
         return make_float3(0.f, 0.f, 0.f);
     const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
               k = min((int)(w + 0.5), F.nz - 1);
-    const float4 b = F.map[((size_t)k * F.ny + j) * F.nx + i];
+    const float4 b = F.nodes[((size_t)k * F.ny + j) * F.nx + i];
     return make_float3(b.x, b.y, b.z);
 }
 
