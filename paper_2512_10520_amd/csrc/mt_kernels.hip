@@ -1350,7 +1350,7 @@ hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
     const bool map = T.field.map != nullptr;
     const bool ldsh = adjoint_lds_history(T);
     size_t shm = (size_t)((T.lds.bytes + 15) & ~15) + (size_t)T.geom.n_mag * block * sizeof(double);
-    if (ldsh) shm += (size_t)kCkptEvery * 3 * block * sizeof(float);
+    if (ldsh) shm += (size_t)kCkptEvery * 6 * block * sizeof(float);   // p0 and a0 per step
     char *sc = reinterpret_cast<char *>(scratch);
     if (map)
         hipLaunchKernelGGL((k_adjoint<true, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
