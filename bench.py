@@ -68,6 +68,10 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-design", action="store_true")
     ap.add_argument("--cpu-muons", type=int, default=1_000_000)
+    ap.add_argument("--gather-sweep", action="store_true",
+                    help="only measure random-gather rates over a range of table sizes")
+    ap.add_argument("--no-gather", action="store_true",
+                    help="skip the gather-ceiling microbenchmark")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM byte counters)")
     return ap.parse_args()
@@ -113,6 +117,12 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.gather_sweep:
+        rates = {f"{w}B@{b / 2 ** 20:.1f}MiB": gather_rate(torch, b, w)
+                 for w, b in ((4, 1 << 19), (4, 3774874), (4, 10 << 20), (4, 11429478),
+                              (16, 48023552), (16, 392 << 20))}
+        print(json.dumps({"gather_loads_per_s": rates}), flush=True)
         return
 
     from paper_2512_10520_amd import api
@@ -200,12 +210,53 @@ def main():
                                  "muon_steps_per_pass": st,
                                  "muon_steps_per_s": st / (oms * 1e-3)}
 
+    if not args.no_gather and args.config == "block":
+        line["gather_ceiling"] = gather_ceiling(torch, value)
+
     if not args.no_design and args.config == "block":
         line["design_step"] = design_step(api, W, torch)
 
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_muons)
     print(json.dumps(line), flush=True)
+
+
+def gather_rate(torch, nbytes, width, loads=256, reps=3):
+    """Independent uniformly random loads of `width` bytes per second from an
+    `nbytes` buffer at full occupancy (libmt_gbench.so)."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2512_10520_amd", "libmt_gbench.so"))
+    lib.mtb_gather.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_uint32,
+                               C.c_void_p, C.c_void_p]
+    buf = torch.randint(0, 2 ** 31 - 1, (nbytes // 4,), dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    blocks = 256 * 8                      # 256 CUs x 8 blocks of 256 threads
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        if lib.mtb_gather(buf.data_ptr(), nbytes, width, loads, blocks, 12345, sink.data_ptr(),
+                          stream) != 0:
+            raise RuntimeError("gather microbenchmark launch failed")
+
+    run()
+    _, ms = _time_launches(run, reps, torch)
+    return blocks * 256 * loads / (ms * 1e-3)
+
+
+def gather_ceiling(torch, value):
+    """The block path's gather roofline: its draw makes about one dependent
+    table load per material step (the 8-byte guide entry; a probe of the
+    cumulative counts for ~2 % of draws), and its tables are L2-resident in
+    practice (99 % L2 hits), so the ceiling is R_gather at an L2-resident
+    buffer of 3.6 MiB (one material's cumulative counts) divided by 1.02
+    gathers per step."""
+    nbytes = 3774874
+    r4 = gather_rate(torch, nbytes, 4)
+    gathers_per_step = 1.02
+    ceiling = r4 / gathers_per_step
+    return {"r_gather_loads_per_s": r4, "buffer_bytes": nbytes, "load_bytes": 4,
+            "gathers_per_step": gathers_per_step, "ceiling_muon_steps_per_s": ceiling,
+            "frac": value / ceiling}
 
 
 def per_variant_plain(api, dm, wl, scales, torch, reps=2):

@@ -16,6 +16,9 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libmt.so")
 SOURCES = ["mt_api.hip", "mt_kernels.hip"]
+# Measurement helper (gather microbenchmark), a library of its own.
+GBENCH_LIB = os.path.join(PKG, "libmt_gbench.so")
+GBENCH_SOURCES = ["gbench.hip"]
 ARCH = os.environ.get("MT_OFFLOAD_ARCH", "gfx950")
 
 
@@ -26,11 +29,11 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build(verbose: bool = False) -> str:
+def _compile(sources, out, verbose):
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", HERE,
-           "-o", LIB + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES]
+           "-o", out + ".tmp"] + [os.path.join(HERE, s) for s in sources]
     if verbose:
         cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -39,7 +42,13 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed with exit code {res.returncode}")
     if verbose:
         sys.stderr.write(res.stderr)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libmt.so (the transport) and libmt_gbench.so (measurement)."""
+    _compile(SOURCES, LIB, verbose)
+    _compile(GBENCH_SOURCES, GBENCH_LIB, False)
     return LIB
 
 
