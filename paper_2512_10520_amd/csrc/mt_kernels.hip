@@ -904,14 +904,17 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) {
 // Gradient of l . g_u(p) with g_u(p) = p_z u + A x u + (A.u) A / (|p| + p_z),
 // A = (-p_y, p_x, 0): the kick is p -> p + g_u(p).
 __device__ __forceinline__ float3 kick_adjoint_corr(float3 p, float3 u, float3 l) {
-    const float P = sqrtf(norm2(p));
+    // hardware reciprocal square root and reciprocal: these are FP32
+    // corrections to an FP64 adjoint, where 1-ulp accuracy is ample
+    const float p2 = norm2(p);
+    const float invP = __builtin_amdgcn_rsqf(p2);
+    const float P = p2 * invP;
     const float D = P + p.z;
     const float alpha = fmaf(-p.y, u.x, p.x * u.y);
     const float beta = fmaf(-p.y, l.x, p.x * l.y);
     const float3 v = cross3(u, l);
-    const float invD = 1.0f / D;
+    const float invD = __builtin_amdgcn_rcpf(D);
     const float Q = alpha * beta * invD;
-    const float invP = 1.0f / P;
     float3 g;
     g.x = v.y + (beta * u.y + alpha * l.y) * invD - Q * invD * (p.x * invP);
     g.y = -v.x + (-beta * u.x - alpha * l.x) * invD - Q * invD * (p.y * invP);
