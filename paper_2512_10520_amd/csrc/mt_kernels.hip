@@ -156,6 +156,8 @@ struct Lane {
     int32_t k, status, ibin, slab, vol, bvol, var;
     PhiloxPrefix ph;
     int64_t g;
+    int32_t mcell;        // field-map cell whose corner values are in mc (-1: none)
+    float mc[24];         // its 8 corners (bx, by, bz), corner order of the cell record
 };
 
 __device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, const DevRun &R) {
@@ -457,6 +459,46 @@ __device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const 
     return add_map<MAP>(T, box_field(T, S, R, vol, var), x, y, z);
 }
 
+// Trilinear map at the lane's position with the current cell's corners kept
+// in registers: consecutive 2 cm steps mostly stay in one cell, so the 128-byte
+// record is loaded only when the lane enters a new cell.  Same values and
+// arithmetic as map_cell + trilerp.
+__device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, float3 B) {
+    const double u = (L.x - F.lo[0]) * F.inv_d[0];
+    const double v = (L.y - F.lo[1]) * F.inv_d[1];
+    const double w = (L.z - F.lo[2]) * F.inv_d[2];
+    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
+          w >= 0.0 && w <= (double)(F.nz - 1)))
+        return B;
+    const int i = min((int)u, F.nx - 2), j = min((int)v, F.ny - 2), k = min((int)w, F.nz - 2);
+    const int cell = (k * (F.ny - 1) + j) * (F.nx - 1) + i;
+    if (cell != L.mcell) {
+        const float4 *b = F.map + (size_t)cell * 8;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float4 q = b[c];
+            L.mc[3 * c] = q.x;
+            L.mc[3 * c + 1] = q.y;
+            L.mc[3 * c + 2] = q.z;
+        }
+        L.mcell = cell;
+    }
+    Corner8 c;
+    c.fx = (float)(u - (double)i);
+    c.fy = (float)(v - (double)j);
+    c.fz = (float)(w - (double)k);
+    c.c000 = make_float4(L.mc[0], L.mc[1], L.mc[2], 0.f);
+    c.c100 = make_float4(L.mc[3], L.mc[4], L.mc[5], 0.f);
+    c.c010 = make_float4(L.mc[6], L.mc[7], L.mc[8], 0.f);
+    c.c110 = make_float4(L.mc[9], L.mc[10], L.mc[11], 0.f);
+    c.c001 = make_float4(L.mc[12], L.mc[13], L.mc[14], 0.f);
+    c.c101 = make_float4(L.mc[15], L.mc[16], L.mc[17], 0.f);
+    c.c011 = make_float4(L.mc[18], L.mc[19], L.mc[20], 0.f);
+    c.c111 = make_float4(L.mc[21], L.mc[22], L.mc[23], 0.f);
+    const float3 m = trilerp(c);
+    return make_float3(B.x + m.x, B.y + m.y, B.z + m.z);
+}
+
 // Nearest-node lookup of the map: the node closest to (x, y, z) on every axis
 // (half-way points take the higher node), zero outside the grid.  One
 // 16-byte load from the node-major copy of the map.
@@ -693,7 +735,11 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         L.bz = b.z;
         L.bvol = vol;
     }
-    const float3 B = map_field<F>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
+    float3 B;
+    if constexpr ((F & kMap) != 0 && (F & kNearest) == 0)
+        B = add_map_cached(L, T.field, make_float3(L.bx, L.by, L.bz));
+    else
+        B = map_field<F>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
     if constexpr ((F & kStages) != 0) rk4_stages<F>(L, B, T, S, R, sc);
     else rk4(L, B, sc);
     ++L.k;
@@ -807,6 +853,7 @@ __device__ __forceinline__ void unpack_rec(Lane &L, const MoveRec &m, int32_t k,
     L.k = k;
     L.status = MT_ST_RUNNING;
     L.bvol = -2;                // caches are rebuilt from the moved hints
+    L.mcell = -1;
     L.zlo = INFINITY;
     L.zhi = -INFINITY;
     L.e2lo = INFINITY;
