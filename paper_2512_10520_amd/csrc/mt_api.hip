@@ -860,8 +860,9 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
     // lookup touches one cache line instead of four.
     const size_t cx = (size_t)nx - 1, cy = (size_t)ny - 1, cz = (size_t)nz - 1;
     const size_t cells = cx * cy * cz;
-    if (cells > 0x7FFFFFFFull)
-        return fail(MT_ERR_LIMIT, "the field map has %zu cells, more than 2^31 - 1", cells);
+    if ((size_t)nx * ny * nz > 0x7FFFFFFFull)
+        return fail(MT_ERR_LIMIT, "the field map has %zu nodes, more than 2^31 - 1",
+                    (size_t)nx * ny * nz);
     std::vector<float4> m;
     try {
         m.resize(cells * 8);

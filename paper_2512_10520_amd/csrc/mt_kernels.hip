@@ -499,6 +499,28 @@ __device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, flo
     return make_float3(B.x + m.x, B.y + m.y, B.z + m.z);
 }
 
+// Nearest node with the last node's value kept in registers (mcell holds the
+// node index, mc[0..2] its value).
+__device__ __forceinline__ float3 add_nearest_cached(Lane &L, const DevField &F, float3 B) {
+    const double u = (L.x - F.lo[0]) * F.inv_d[0];
+    const double v = (L.y - F.lo[1]) * F.inv_d[1];
+    const double w = (L.z - F.lo[2]) * F.inv_d[2];
+    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
+          w >= 0.0 && w <= (double)(F.nz - 1)))
+        return B;
+    const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
+              k = min((int)(w + 0.5), F.nz - 1);
+    const int node = (k * F.ny + j) * F.nx + i;
+    if (node != L.mcell) {
+        const float4 q = F.nodes[node];
+        L.mc[0] = q.x;
+        L.mc[1] = q.y;
+        L.mc[2] = q.z;
+        L.mcell = node;
+    }
+    return make_float3(B.x + L.mc[0], B.y + L.mc[1], B.z + L.mc[2]);
+}
+
 // Nearest-node lookup of the map: the node closest to (x, y, z) on every axis
 // (half-way points take the higher node), zero outside the grid.  One
 // 16-byte load from the node-major copy of the map.
@@ -738,6 +760,8 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
     float3 B;
     if constexpr ((F & kMap) != 0 && (F & kNearest) == 0)
         B = add_map_cached(L, T.field, make_float3(L.bx, L.by, L.bz));
+    else if constexpr ((F & kNearest) != 0)
+        B = add_nearest_cached(L, T.field, make_float3(L.bx, L.by, L.bz));
     else
         B = map_field<F>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
     if constexpr ((F & kStages) != 0) rk4_stages<F>(L, B, T, S, R, sc);
