@@ -26,7 +26,6 @@ METRIC = "muon-steps/sec on 1 MI355X vs CPU FP64 oracle; fwd+adjoint time per de
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-ops/s; the
 # 157.3 TFLOP/s fp32 figure is this x 2 (FMA) x 2 (dual issue / packed).
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
-HBM_PEAK = 8.0e12
 
 # Algorithmic operations of one muon step, counted from the method at the
 # granularity of single hardware operations (the design doc lists them): break
@@ -168,20 +167,12 @@ def main():
     lanes = int(out.n_steps.numel())
     kernel = "k_persistent" if mode == "persistent" else "k_plain"
     traffic = measured_traffic(kernel, args.config)
-    if args.config == "shield" and args.interp == "trilinear" and not args.stage_field:
-        # HBM-bound: eight map corners per step do not fit the L2
-        alg_bytes = algorithmic_bytes(args.config, steps_per_pass, lanes)
-        achieved = alg_bytes / (ev_ms * 1e-3)
-        roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": traffic,
-                    "kernel": kernel, "kernel_ms": ev_ms, "bytes_per_pass": alg_bytes}
-    else:
-        alg_ops = algorithmic_ops(args.config, steps_per_pass, lanes)
-        achieved = alg_ops / (ev_ms * 1e-3)
-        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                    "unit": "Tops/s (VALU lane-ops)", "frac": achieved / VALU_LANE_OPS_PEAK,
-                    "traffic": traffic, "kernel": kernel, "kernel_ms": ev_ms,
-                    "ops_per_pass": alg_ops}
+    alg_ops = algorithmic_ops(args.config, steps_per_pass, lanes)
+    achieved = alg_ops / (ev_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
+                "unit": "Tops/s (VALU lane-ops)", "frac": achieved / VALU_LANE_OPS_PEAK,
+                "traffic": traffic, "kernel": kernel, "kernel_ms": ev_ms,
+                "ops_per_pass": alg_ops}
     line = {"metric": METRIC, "value": value, "unit": "muon-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -289,14 +280,6 @@ def algorithmic_ops(config, steps, lanes):
     if config == "blocks":
         return steps * (OPS["material"] + OPS["block_lookup"])
     return steps * (OPS["material"] + OPS["map"])
-
-
-def algorithmic_bytes(config, steps, lanes):
-    """Bytes one pass must move at least (shield): per step the eight corner
-    values of the field-map cell (8 x 12 B) and the guide entry of the draw
-    (8 B, every step counted as a material step), plus each muon's 49 B in and
-    60 B out once."""
-    return steps * (8 * 12 + 8) + lanes * (49 + 60)
 
 
 def measured_traffic(kernel, config):
