@@ -245,9 +245,13 @@ def gather_ceiling(torch, value):
     r4 = gather_rate(torch, nbytes, 4)
     gathers_per_step = 1.02
     ceiling = r4 / gathers_per_step
+    # The method's own gathers: a binary search over the 10^4 cumulative
+    # counts of a histogram is 14 dependent probes per material step.
+    search_gathers = 14
     return {"r_gather_loads_per_s": r4, "buffer_bytes": nbytes, "load_bytes": 4,
             "gathers_per_step": gathers_per_step, "ceiling_muon_steps_per_s": ceiling,
-            "frac": value / ceiling}
+            "frac": value / ceiling, "search_gathers_per_step": search_gathers,
+            "frac_of_search_ceiling": value * search_gathers / r4}
 
 
 def per_variant_plain(api, dm, wl, scales, torch, reps=2):
