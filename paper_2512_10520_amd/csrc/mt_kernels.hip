@@ -453,12 +453,6 @@ __device__ __forceinline__ float3 add_map(const Tables &T, float3 B, double x, d
     return B;
 }
 
-template <bool MAP>
-__device__ __forceinline__ float3 field_at(const Tables &T, const Lds &S, const DevRun &R, int vol,
-                                           int var, double x, double y, double z) {
-    return add_map<MAP>(T, box_field(T, S, R, vol, var), x, y, z);
-}
-
 // Trilinear map at the lane's position with the current cell's corners kept
 // in registers: consecutive 2 cm steps mostly stay in one cell, so the 128-byte
 // record is loaded only when the lane enters a new cell.  Same values and
