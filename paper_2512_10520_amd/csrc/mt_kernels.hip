@@ -723,8 +723,11 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         float f = fmaf((float)il + v1, T.hist.loss_w, T.hist.loss_lo);
         float tau = fmaf((float)is + v2, T.hist.scat_w, T.hist.scat_lo);
         if constexpr ((F & kLog) != 0) {      // jitter uniform in log10 of the value
-            if (T.hist.log_loss) f = exp10f(f);
-            if (T.hist.log_scat) tau = exp10f(tau);
+            // 10^u = 2^(u log2 10) on the hardware exp2 (relative error ~1e-6
+            // for |u| <= 7, far inside the FP32 kick arithmetic around it)
+            constexpr float kLog2Of10 = 3.32192809488736f;
+            if (T.hist.log_loss) f = __builtin_amdgcn_exp2f(f * kLog2Of10);
+            if (T.hist.log_scat) tau = __builtin_amdgcn_exp2f(tau * kLog2Of10);
         }
         // v_sin_f32 / v_cos_f32 take their argument in revolutions: sin(2 pi v3).
         const float sn = __builtin_amdgcn_sinf(v3);
