@@ -22,13 +22,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "muon-steps/sec on 1 MI355X vs CPU FP64 oracle; fwd+adjoint time per design step"
 
-# MI355X published peaks and the issue rate they imply (the design doc derives it):
+# MI355X published peaks and the issue rate they imply:
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-ops/s; the
 # 157.3 TFLOP/s fp32 figure is this x 2 (FMA) x 2 (dual issue / packed).
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 # Algorithmic operations of one muon step, counted from the method at the
-# granularity of single hardware operations (the design doc lists them): break
+# granularity of single hardware operations: break
 # test 8, box lookup 6, momentum bin 2, Philox4x32-10 53 (18 32x32->64
 # products + 35 xors once the muon-constant part of rounds 1-2 is hoisted),
 # inverse CDF 7, cell split 3, jitter + azimuth 18, kick + rotation 30,
