@@ -78,6 +78,23 @@ def test_scan_variants_parity():
         print("scan", v, s)
 
 
+def test_scan_variants_plain_launch():
+    """The one-launch plain form of the scan (all variants of every muon, an
+    even and an odd variant count) against the oracle and bitwise against the
+    persistent form."""
+    for v in (4, 3):
+        wl = W.make_workload("scan", n_muons=2500, n_variants=v)
+        n = len(wl.muons)
+        g = gpu_run(wl, mode="plain")
+        gp = gpu_run(wl, mode="persistent")
+        for k in g:
+            assert np.array_equal(g[k], gp[k]), (v, k)
+        for var in range(v):
+            o = oracle_run(wl, np.arange(n), variant=var)
+            s = compare(g, o, sel=np.arange(var * n, (var + 1) * n), label=f"scan plain v={var}/{v}")
+            print("scan plain", v, var, s)
+
+
 def test_persistent_matches_plain_bitwise():
     wl = W.make_workload("block", n_muons=50_000)
     a = gpu_run(wl, mode="plain")
