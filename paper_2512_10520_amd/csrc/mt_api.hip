@@ -319,7 +319,20 @@ std::vector<unsigned char> tune_key(const mt_params *p, int64_t n) {
         int64_t n;
         int32_t nv, max_steps, has_map, mode;
         double step, pmin;
-    } k{n, p->n_variants, p->max_steps, g.T.field.map != nullptr, p->mode, p->step_m, p->p_min};
+        int32_t sampler, interp, stage_field, blocks;   // the kernel variant
+    } k;
+    std::memset(&k, 0, sizeof(k));
+    k.n = n;
+    k.nv = p->n_variants;
+    k.max_steps = p->max_steps;
+    k.has_map = g.T.field.map != nullptr;
+    k.mode = p->mode;
+    k.step = p->step_m;
+    k.pmin = p->p_min;
+    k.sampler = p->sampler;
+    k.interp = p->interp;
+    k.stage_field = p->stage_field;
+    k.blocks = g.T.geom.n_poly > 0;
     return make_key(&k, sizeof(k));
 }
 
