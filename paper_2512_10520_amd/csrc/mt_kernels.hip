@@ -1013,8 +1013,8 @@ template <bool MAP>
 __device__ __forceinline__ void reverse_step(const Tables &T, const Lds &S, const DevRun &R,
                                              const StepConst &sc, float kq, float3 p0, float3 a0,
                                              double rx, double ry, double rz, int vol, float3 u,
-                                             float3 Bbox, double lr[3], double lp[3], double *sgs,
-                                             int bd) {
+                                             float3 Bbox, double lr[3], double lp[3], int &mag_out,
+                                             double &dsg) {
     const int mat = vol >= 0 ? S.mat[vol] : -1;
     const float3 B = add_map<MAP>(T, Bbox, rx, ry, rz);
     const float3 Lr = make_float3((float)lr[0], (float)lr[1], (float)lr[2]);
@@ -1069,11 +1069,14 @@ __device__ __forceinline__ void reverse_step(const Tables &T, const Lds &S, cons
     lp[0] = la0[0];
     lp[1] = la0[1];
     lp[2] = la0[2];
+    mag_out = -1;
+    dsg = 0.0;
     if (vol >= 0) {
         const int m = S.mag[vol];
         if (m >= 0) {
             const float4 b = S.bf[vol];
-            sgs[m * bd] += (double)fmaf(lB.x, b.x, fmaf(lB.y, b.y, lB.z * b.z));
+            mag_out = m;
+            dsg = (double)fmaf(lB.x, b.x, fmaf(lB.y, b.y, lB.z * b.z));
         }
     }
     if (MAP) {
@@ -1160,26 +1163,27 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
             const float4 *rec = reinterpret_cast<const float4 *>(R.tape) + (size_t)k0 * lanes + g;
             L.bvol = -2;
             // history of the segment: p0 (pre-kick) and a0 (stage-0) momenta
-            // per step, [step][6][lane] in LDS (LDSH) or device memory
+            // per step, [step][6][thread] floats in LDS (LDSH), or in device
+            // memory as float4 (p0, a0.x) and float2 (a0.y, a0.z) per (step, lane)
             float *hp;
             int64_t hs;
             if (LDSH) {
                 hp = hist;
                 hs = bd;
             } else {
-                hp = reinterpret_cast<float *>(scratch) + g;
-                hs = lanes;
+                hp = nullptr;
+                hs = 0;
             }
+            // device memory: float4 (p0, a0.x) and float2 (a0.y, a0.z) per (step, lane)
+            float4 *h4 = reinterpret_cast<float4 *>(scratch) + g;
+            float2 *h2 = reinterpret_cast<float2 *>(scratch + (size_t)kCkptEvery * 16 * lanes) + g;
             double *hr = reinterpret_cast<double *>(
                 scratch + (size_t)kCkptEvery * 6 * sizeof(float) * lanes) + g;
             float4 next = rec[0];
             for (int k = k0; k < k1; ++k) {
                 const float4 cur = next;
                 if (k + 1 < k1) next = rec[(size_t)(k + 1 - k0) * lanes];
-                float *h = hp + (size_t)(k - k0) * 6 * hs;
-                h[0] = (float)L.px;
-                h[hs] = (float)L.py;
-                h[2 * hs] = (float)L.pz;
+                const float p0x = (float)L.px, p0y = (float)L.py, p0z = (float)L.pz;
                 if (MAP) {
                     double *hh = hr + (size_t)(k - k0) * 3 * lanes;
                     hh[0] = L.x;
@@ -1187,17 +1191,38 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
                     hh[2 * lanes] = L.z;
                 }
                 const float3 a0 = replay_step<MAP>(L, T, S, R, sc, var, cur);
-                h[3 * hs] = a0.x;
-                h[4 * hs] = a0.y;
-                h[5 * hs] = a0.z;
+                if (LDSH) {
+                    float *h = hp + (size_t)(k - k0) * 6 * hs;
+                    h[0] = p0x;
+                    h[hs] = p0y;
+                    h[2 * hs] = p0z;
+                    h[3 * hs] = a0.x;
+                    h[4 * hs] = a0.y;
+                    h[5 * hs] = a0.z;
+                } else {
+                    h4[(size_t)(k - k0) * lanes] = make_float4(p0x, p0y, p0z, a0.x);
+                    h2[(size_t)(k - k0) * lanes] = make_float2(a0.y, a0.z);
+                }
             }
             int bvol = -2;
             float3 bb = make_float3(0.f, 0.f, 0.f);
+            int acc_m = -1;
+            double acc = 0.0;
             next = rec[(size_t)(k1 - 1 - k0) * lanes];
             for (int k = k1 - 1; k >= k0; --k) {
                 const float4 cur = next;
                 if (k > k0) next = rec[(size_t)(k - 1 - k0) * lanes];
-                const float *h = hp + (size_t)(k - k0) * 6 * hs;
+                float3 p0, a0;
+                if (LDSH) {
+                    const float *h = hp + (size_t)(k - k0) * 6 * hs;
+                    p0 = make_float3(h[0], h[hs], h[2 * hs]);
+                    a0 = make_float3(h[3 * hs], h[4 * hs], h[5 * hs]);
+                } else {
+                    const float4 A = h4[(size_t)(k - k0) * lanes];
+                    const float2 Bv = h2[(size_t)(k - k0) * lanes];
+                    p0 = make_float3(A.x, A.y, A.z);
+                    a0 = make_float3(A.w, Bv.x, Bv.y);
+                }
                 double rx = 0.0, ry = 0.0, rz = 0.0;
                 if (MAP) {
                     const double *hh = hr + (size_t)(k - k0) * 3 * lanes;
@@ -1210,10 +1235,19 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
                     bb = box_field(T, S, R, vol, var);
                     bvol = vol;
                 }
-                reverse_step<MAP>(T, S, R, sc, kq, make_float3(h[0], h[hs], h[2 * hs]),
-                                  make_float3(h[3 * hs], h[4 * hs], h[5 * hs]), rx, ry, rz, vol,
-                                  make_float3(cur.x, cur.y, cur.z), bb, lr, lp, sgs, bd);
+                int m;
+                double d;
+                reverse_step<MAP>(T, S, R, sc, kq, p0, a0, rx, ry, rz, vol,
+                                  make_float3(cur.x, cur.y, cur.z), bb, lr, lp, m, d);
+                // scale gradient: accumulate in a register while the magnet is unchanged
+                if (m != acc_m) {
+                    if (acc_m >= 0) sgs[acc_m * bd] += acc;
+                    acc_m = m;
+                    acc = 0.0;
+                }
+                acc += d;
             }
+            if (acc_m >= 0) sgs[acc_m * bd] += acc;
         }
     }
     for (int a = 0; a < 3; ++a) {
