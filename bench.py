@@ -38,7 +38,10 @@ VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 # the straight-line update (-84).  A convex-block lookup replaces the box
 # lookup by one candidate's sign test (grid cell 9, slice 8 FMAs, 4 edge
 # products 24, sign logic 8: +43 over the cached box lookup).
-OPS = {"material": 233, "vacuum": 40, "map": 30, "straight": -84, "block_lookup": 43}
+# In the variant-wave form the 64 variants of a muon share one Philox block
+# per step, so a lane's share of it is 53/64 ~ 1 operation (-52).
+OPS = {"material": 233, "vacuum": 40, "map": 30, "straight": -84, "block_lookup": 43,
+       "philox_shared": -52}
 
 WORKLOADS = {
     "tiny": "tiny: 1 iron box 1 m, no field, 32x64x64 histograms, 10^4 muons at 100 GeV",
@@ -56,7 +59,10 @@ def _parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="block", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="auto", choices=["auto", "plain", "persistent"])
+    ap.add_argument("--mode", default="auto",
+                    choices=["auto", "plain", "persistent", "variant_waves"],
+                    help="auto: time every form the workload admits and report the fastest "
+                         "(variant_waves needs a multiple of 64 variants)")
     ap.add_argument("--sampler", default="cdf", choices=["cdf", "alias"],
                     help="histogram-cell sampler of the timed pass (the other one is timed "
                          "beside it on the block workload)")
@@ -139,13 +145,16 @@ def main():
     def spec_for(mode, sampler=args.sampler):
         return api.RunSpec.from_workload(wl, mode=mode, sampler=sampler, interp=args.interp,
                                          stage_field=args.stage_field,
-                                         use_graph=use_graph and mode == "persistent")
+                                         use_graph=use_graph and mode != "plain")
 
-    modes = ["plain", "persistent"] if args.mode == "auto" else [args.mode]
-    if "persistent" in modes:
-        tuned = api.autotune(dm, spec_for("persistent"), scales=scales)
+    if args.mode == "auto":
+        modes = ["plain", "persistent"]
+        if wl.run.n_variants % 64 == 0:
+            modes.append("variant_waves")
     else:
-        tuned = None
+        modes = [args.mode]
+    tuned = {m: api.autotune(dm, spec_for(m), scales=scales)
+             for m in modes if m != "plain"} or None
     outs = {m: api.alloc_result(spec_for(m), len(dm), "cuda") for m in modes}
     probe = {}
     for m in modes:
@@ -165,9 +174,10 @@ def main():
                                  args.steps, torch)
     value = steps_per_pass * args.steps / wall
     lanes = int(out.n_steps.numel())
-    kernel = "k_persistent" if mode == "persistent" else "k_plain"
+    kernel = {"plain": "k_plain", "persistent": "k_persistent",
+              "variant_waves": "k_variant_waves"}[mode]
     traffic = measured_traffic(kernel, args.config)
-    alg_ops = algorithmic_ops(args.config, steps_per_pass, lanes)
+    alg_ops = algorithmic_ops(args.config, steps_per_pass, lanes, mode)
     achieved = alg_ops / (ev_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
                 "unit": "Tops/s (VALU lane-ops)", "frac": achieved / VALU_LANE_OPS_PEAK,
@@ -272,18 +282,20 @@ def per_variant_plain(api, dm, wl, scales, torch, reps=2):
     return ms
 
 
-def algorithmic_ops(config, steps, lanes):
+def algorithmic_ops(config, steps, lanes, mode="plain"):
     """Algorithmic operations of one pass (see OPS).  block/scan/diff: the
     first step of every muon starts in vacuum before the box; tiny: zero
     field; shield: every step is counted as a material step with a map
-    lookup (an upper bound: the air gaps are vacuum)."""
+    lookup (an upper bound: the air gaps are vacuum).  The variant-wave form
+    shares the Philox block of a material step among 64 lanes."""
+    mat = OPS["material"] + (OPS["philox_shared"] if mode == "variant_waves" else 0)
     if config in ("block", "scan", "diff", "logbins"):
-        return (steps - lanes) * OPS["material"] + lanes * OPS["vacuum"]
+        return (steps - lanes) * mat + lanes * OPS["vacuum"]
     if config == "tiny":
-        return (steps - lanes) * (OPS["material"] + OPS["straight"]) + lanes * OPS["vacuum"]
+        return (steps - lanes) * (mat + OPS["straight"]) + lanes * OPS["vacuum"]
     if config == "blocks":
-        return steps * (OPS["material"] + OPS["block_lookup"])
-    return steps * (OPS["material"] + OPS["map"])
+        return steps * (mat + OPS["block_lookup"])
+    return steps * (mat + OPS["map"])
 
 
 def measured_traffic(kernel, config):

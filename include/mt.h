@@ -61,6 +61,10 @@ extern "C" {
 /* ---- launch forms ------------------------------------------------------ */
 #define MT_MODE_PLAIN       0    /* one lane per muon until it stops */
 #define MT_MODE_PERSISTENT  1    /* resident grid, atomic work queue, compaction */
+#define MT_MODE_VARIANT_WAVES 2  /* each wavefront transports 64 variants of one muon, which
+                                    share the muon's random stream: one Philox block per lane
+                                    per 64 steps instead of one per step; needs
+                                    n_variants % 64 == 0, no trace */
 
 /* ---- samplers of the histogram cell ------------------------------------ */
 #define MT_SAMPLER_CDF      0    /* exact inverse CDF over integer counts */
@@ -225,10 +229,11 @@ typedef struct mt_params {
     uint64_t seed;
     int32_t  n_variants;      /* >= 1 */
     const float *scales;      /* device [n_variants][n_mag] or NULL (all 1) */
-    int32_t  mode;            /* MT_MODE_PLAIN / MT_MODE_PERSISTENT */
+    int32_t  mode;            /* MT_MODE_PLAIN / MT_MODE_PERSISTENT / MT_MODE_VARIANT_WAVES */
     int32_t  block;           /* threads per block, multiple of 64 in [64, 1024]; 0 = default */
     int32_t  compact_every;   /* persistent: steps between refills, >= 1; 0 = default */
-    int32_t  use_graph;       /* persistent: capture the launch once as a hipGraph and replay */
+    int32_t  use_graph;       /* persistent and variant-wave forms: capture the launch once
+                                 as a hipGraph and replay */
     /* differentiable form */
     int32_t  ckpt_every;      /* 0 = off, or 16: checkpoint (r, p) every 16 steps */
     double  *ckpt;            /* device [ceil(max_steps/16)][6][lanes] */
@@ -288,10 +293,11 @@ int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in
 /*
  * Pick block size and refill interval of the persistent form by timing
  * candidate launches of this exact call (blocks {64,128,256,512} x refill
- * intervals {4,8,16,32,64,128}) on the caller's stream.  Outputs are
- * overwritten (every candidate writes identical bits).  The choice is
- * returned and remembered for later calls with compact_every = 0 and
- * block = 0 on the same workload shape.
+ * intervals {4,8,16,32,64,128}) on the caller's stream; for
+ * MT_MODE_VARIANT_WAVES only the block size is tuned (best_compact gets 0).
+ * Outputs are overwritten (every candidate writes identical bits).  The
+ * choice is returned and remembered for later calls with compact_every = 0
+ * and block = 0 on the same workload shape.
  */
 int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
                 mt_result *res, void *hip_stream, int32_t *best_block,

@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("MT_LIBRARY") or os.path.join(_HERE, "libmt.so")
 MT_OK = 0
 ERRORS = {-1: "MT_ERR_INVALID_ARG", -2: "MT_ERR_SHAPE", -3: "MT_ERR_EMPTY_HIST",
           -4: "MT_ERR_NOT_LOADED", -5: "MT_ERR_OOM", -6: "MT_ERR_HIP", -7: "MT_ERR_LIMIT"}
-MT_MODE_PLAIN, MT_MODE_PERSISTENT = 0, 1
+MT_MODE_PLAIN, MT_MODE_PERSISTENT, MT_MODE_VARIANT_WAVES = 0, 1, 2
 MT_SAMPLER_CDF, MT_SAMPLER_ALIAS = 0, 1
 MT_INTERP_TRILINEAR, MT_INTERP_NEAREST = 0, 1
 MT_AXIS_LOG_LOSS, MT_AXIS_LOG_SCAT = 1, 2

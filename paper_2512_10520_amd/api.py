@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import MtMuons, MtParams, MtResult, check
 
-MODES = {"plain": _lib.MT_MODE_PLAIN, "persistent": _lib.MT_MODE_PERSISTENT}
+MODES = {"plain": _lib.MT_MODE_PLAIN, "persistent": _lib.MT_MODE_PERSISTENT,
+         "variant_waves": _lib.MT_MODE_VARIANT_WAVES}
 SAMPLERS = {"cdf": _lib.MT_SAMPLER_CDF, "alias": _lib.MT_SAMPLER_ALIAS}
 SAMPLER_NAMES = {v: k for k, v in SAMPLERS.items()}
 INTERPS = {"trilinear": _lib.MT_INTERP_TRILINEAR, "nearest": _lib.MT_INTERP_NEAREST}
@@ -325,15 +326,17 @@ def propagate_backward(muons: DeviceMuons, spec: RunSpec, fwd: Result, g_out: to
 
 def autotune(muons: DeviceMuons, spec: RunSpec, scales=None, out: Optional[Result] = None,
              stream=None):
-    """Time the persistent form's candidate (block, refill interval) pairs on
-    this call and remember the fastest (``mt_autotune``)."""
+    """Time the candidate (block, refill interval) pairs of the persistent
+    form -- or the block sizes of the variant-wave form when ``spec.mode`` is
+    "variant_waves" -- on this call and remember the fastest (``mt_autotune``)."""
     _check_muons(muons)
     scales = _check_scales(scales, spec)
     n = len(muons)
     if out is None:
         out = alloc_result(spec, n, muons.state.device)
     p = _params(spec, scales)
-    p.mode = _lib.MT_MODE_PERSISTENT
+    if spec.mode != "variant_waves":
+        p.mode = _lib.MT_MODE_PERSISTENT
     res = MtResult(out.status.data_ptr(), out.n_steps.data_ptr(), out.volume.data_ptr())
     o = MtMuons(*[out.state[a].data_ptr() for a in range(6)], None)
     i = muons.c_struct()

@@ -186,8 +186,14 @@ int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *
     if (p->max_steps < 0) return fail(MT_ERR_INVALID_ARG, "max_steps must be >= 0");
     if (!(p->p_min >= 0.0) || !std::isfinite(p->p_min))
         return fail(MT_ERR_INVALID_ARG, "p_min must be finite and >= 0");
-    if (p->mode != MT_MODE_PLAIN && p->mode != MT_MODE_PERSISTENT)
+    if (p->mode != MT_MODE_PLAIN && p->mode != MT_MODE_PERSISTENT &&
+        p->mode != MT_MODE_VARIANT_WAVES)
         return fail(MT_ERR_INVALID_ARG, "unknown mode %d", p->mode);
+    if (p->mode == MT_MODE_VARIANT_WAVES && p->n_variants % mt::kWave != 0)
+        return fail(MT_ERR_INVALID_ARG, "MT_MODE_VARIANT_WAVES needs n_variants %% %d == 0 "
+                                        "(got %d)", mt::kWave, p->n_variants);
+    if (p->mode == MT_MODE_VARIANT_WAVES && p->n_trace > 0 && p->trace_steps > 0)
+        return fail(MT_ERR_INVALID_ARG, "MT_MODE_VARIANT_WAVES does not record traces");
     if (p->block != 0 && (p->block < 64 || p->block > 1024 || p->block % 64 != 0))
         return fail(MT_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
     if (p->compact_every < 0) return fail(MT_ERR_INVALID_ARG, "compact_every must be >= 0");
@@ -280,11 +286,12 @@ int enqueue(const mt_params *p, const Call &c, hipStream_t s) {
     if (p->mode == MT_MODE_PERSISTENT) {
         int rc = g.queue.ensure(sizeof(unsigned long long));
         if (rc) return rc;
-        MT_HIP(mt::launch_queue_reset(reinterpret_cast<unsigned long long *>(g.queue.p),
-                                      reinterpret_cast<double *>(g.zero_dummy.p), 0, s));
+        unsigned long long *queue = reinterpret_cast<unsigned long long *>(g.queue.p);
+        MT_HIP(mt::launch_queue_reset(queue, reinterpret_cast<double *>(g.zero_dummy.p), 0, s));
         const int grid = g.cu_count * mt::persistent_blocks_per_cu(g.T, c.block);
-        MT_HIP(mt::launch_persistent(g.T, c.R, c.io, c.block, grid, c.compact,
-                                     reinterpret_cast<unsigned long long *>(g.queue.p), s));
+        MT_HIP(mt::launch_persistent(g.T, c.R, c.io, c.block, grid, c.compact, queue, s));
+    } else if (p->mode == MT_MODE_VARIANT_WAVES) {
+        MT_HIP(mt::launch_variant_waves(g.T, c.R, c.io, c.block, s));
     } else {
         MT_HIP(mt::launch_plain(g.T, c.R, c.io, c.block, s));
     }
@@ -351,7 +358,7 @@ int propagate_impl(const mt_params *p, int64_t n, const mt_muons *in, mt_muons *
         }
         return MT_OK;
     }
-    if (p->mode == MT_MODE_PERSISTENT && p->block == 0 && p->compact_every == 0) {
+    if (p->mode != MT_MODE_PLAIN && p->block == 0 && p->compact_every == 0) {
         if (const TuneEntry *t = find_tuned(tune_key(p, n))) {
             c.block = t->block;
             c.compact = t->compact;
@@ -361,7 +368,7 @@ int propagate_impl(const mt_params *p, int64_t n, const mt_muons *in, mt_muons *
     if (force_compact) c.compact = force_compact;
     rc = prepare_workspace(p, c);
     if (rc) return rc;
-    if (allow_graph && p->use_graph && p->mode == MT_MODE_PERSISTENT) {
+    if (allow_graph && p->use_graph && p->mode != MT_MODE_PLAIN) {
         struct K {
             mt_params p;
             int64_t n;
@@ -969,11 +976,14 @@ int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons
                 float *best_ms) {
     std::lock_guard<std::mutex> lk(g.mu);
     if (!params) return fail(MT_ERR_INVALID_ARG, "params is NULL");
-    if (params->mode != MT_MODE_PERSISTENT)
-        return fail(MT_ERR_INVALID_ARG, "the autotuner tunes MT_MODE_PERSISTENT launches");
+    if (params->mode != MT_MODE_PERSISTENT && params->mode != MT_MODE_VARIANT_WAVES)
+        return fail(MT_ERR_INVALID_ARG, "the autotuner tunes MT_MODE_PERSISTENT and "
+                                        "MT_MODE_VARIANT_WAVES launches");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const int blocks[] = {64, 128, 256, 512};
-    const int compacts[] = {4, 8, 16, 32, 64, 128};
+    const bool waves = params->mode == MT_MODE_VARIANT_WAVES;   // no refill interval to tune
+    const std::vector<int> compacts =
+        waves ? std::vector<int>{16} : std::vector<int>{4, 8, 16, 32, 64, 128};
     hipEvent_t e0, e1;
     MT_HIP(hipEventCreate(&e0));
     MT_HIP(hipEventCreate(&e1));
@@ -1021,7 +1031,7 @@ int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons
     if (!found) g.tuned.push_back(TuneEntry{key, bb, bc});
     drop_graphs();
     if (best_block) *best_block = bb;
-    if (best_compact) *best_compact = bc;
+    if (best_compact) *best_compact = waves ? 0 : bc;
     if (best_ms) *best_ms = best;
     return MT_OK;
 }

@@ -160,16 +160,9 @@ struct Lane {
     float mc[24];         // its 8 corners (bx, by, bz), corner order of the cell record
 };
 
-__device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, const DevRun &R) {
-    int64_t var = 0, j = g;
-    if (R.lanes != R.n) {
-        if (R.lanes <= 0xFFFFFFFFll) {
-            var = (uint32_t)g / (uint32_t)R.n;
-        } else {
-            var = g / R.n;
-        }
-        j = g - var * R.n;
-    }
+// Lane state of output slot g = var * n + j (input muon j, variant var).
+__device__ __forceinline__ void load_lane_at(Lane &L, int64_t j, int64_t var, int64_t g,
+                                             const DevIO &io, const DevRun &R) {
     L.x = io.x[j];
     L.y = io.y[j];
     L.z = io.z[j];
@@ -196,6 +189,19 @@ __device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, c
     const bool ok = isfinite(L.x) && isfinite(L.y) && isfinite(L.z) && isfinite(p2) &&
                     p2 > 0.0 && (qi == 1 || qi == -1);
     if (!ok) L.status = MT_ST_INVALID;
+}
+
+__device__ __forceinline__ void load_lane(Lane &L, int64_t g, const DevIO &io, const DevRun &R) {
+    int64_t var = 0, j = g;
+    if (R.lanes != R.n) {
+        if (R.lanes <= 0xFFFFFFFFll) {
+            var = (uint32_t)g / (uint32_t)R.n;
+        } else {
+            var = g / R.n;
+        }
+        j = g - var * R.n;
+    }
+    load_lane_at(L, j, var, g, io, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -616,7 +622,8 @@ enum : unsigned {
     kStages = 32u,   // field evaluated at every RK4 stage position
     kPoly = 64u,     // convex-block geometry instead of boxes
     kLog = 128u,     // a histogram axis is binned in log10
-    kFeatures = 256u // number of masks
+    kFeatures = 256u,// number of masks
+    kShared = 256u   // the step's Philox words come from the caller (not a mask bit)
 };
 
 // Masks that have a kernel: the tape belongs to the differentiable form,
@@ -689,7 +696,7 @@ __device__ __forceinline__ void rk4_stages(Lane &L, float3 B1, const Tables &T, 
 // ---------------------------------------------------------------------------
 template <unsigned F>
 __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, const DevRun &R,
-                                        const StepConst &sc) {
+                                        const StepConst &sc, uint4 w_shared = uint4{}) {
     constexpr bool MAP = (F & kMap) != 0, TAPE = (F & kTape) != 0, TRACE = (F & kTrace) != 0;
     const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
     // Break test in the order p_min, z_max, x_max, y_max, step cap (the first
@@ -711,7 +718,9 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
     int cell = -1;
     if (mat >= 0) {
         const int ibin = bin_of(L, T, S, p2);
-        const uint4 w = philox_step(L.ph, (uint32_t)L.k, R.key0, R.key1);
+        uint4 w;
+        if constexpr ((F & kShared) != 0) w = w_shared;
+        else w = philox_step(L.ph, (uint32_t)L.k, R.key0, R.key1);
         const int h = mat * T.hist.n_pbin + ibin;
         if constexpr ((F & kAlias) != 0) cell = alias_cell(T.hist, h, w);
         else cell = sample_cell(T.hist, S, h, w.x);
@@ -938,6 +947,53 @@ __global__ void __launch_bounds__(1024) k_persistent(Tables T, DevRun R, DevIO i
             if (total == 0) break;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Variant-wave form (field variants of the same muons).  All variants of
+// muon j draw the same random words at step k, so a wavefront that holds 64
+// variants of one muon needs one Philox block per step, not 64: every 64
+// steps lane l forms the block of step k + l, and at step k every lane takes
+// the four words from lane k mod 64 (v_readlane).  The lanes of such a
+// wavefront step in lockstep (all start at step 0, and each pass of the loop
+// is one step for every lane still running), which is what makes the shared
+// block the right one; a lane whose muon has stopped still forms its block
+// for the others.  Wavefront w of the grid takes item w = (muon j, group of
+// 64 variants).  Results are bit-identical to the other forms (same words,
+// same arithmetic, same output slots).
+// ---------------------------------------------------------------------------
+template <unsigned F>     // F holds neither kTape nor kTrace
+__global__ void __launch_bounds__(1024) k_variant_waves(Tables T, DevRun R, DevIO io) {
+    extern __shared__ __align__(16) char smem[];
+    const Lds S = stage_tables<(F & kPoly) != 0>(smem, T);
+    const StepConst sc = step_const(R);
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int64_t n = R.n;
+    const int64_t groups = R.lanes / n / kWave;      // groups of 64 variants per muon
+    // the item index is the same for the whole wavefront
+    const int64_t it = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (it >= n * groups) return;
+    const int64_t j = it / groups;
+    const int64_t var = (it - j * groups) * kWave + lane;
+    Lane L;
+    load_lane_at(L, j, var, var * n + j, io, R);
+    const PhiloxPrefix P =
+        philox_prefix((uint32_t)j, (uint32_t)((uint64_t)j >> 32), R.key0, R.key1);
+    bool running = L.status == MT_ST_RUNNING;
+    uint4 blk = make_uint4(0u, 0u, 0u, 0u);
+    for (int k = 0; __ballot(running) != 0; ++k) {
+        const int sl = k & (kWave - 1);
+        if (sl == 0) blk = philox_step(P, (uint32_t)(k + lane), R.key0, R.key1);
+        if (running) {
+            const uint4 w = make_uint4((uint32_t)__builtin_amdgcn_readlane((int)blk.x, sl),
+                                       (uint32_t)__builtin_amdgcn_readlane((int)blk.y, sl),
+                                       (uint32_t)__builtin_amdgcn_readlane((int)blk.z, sl),
+                                       (uint32_t)__builtin_amdgcn_readlane((int)blk.w, sl));
+            running = advance<F | kShared>(L, T, S, R, sc, w);
+        }
+    }
+    store_lane(L, T, S, io);
 }
 
 __global__ void k_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero) {
@@ -1359,6 +1415,18 @@ static const void *persistent_kernel() {
     else return nullptr;
 }
 
+template <unsigned F>
+static const void *variant_waves_kernel() {
+    if constexpr (valid_mask(F) && !(F & (kTape | kTrace)))
+        return reinterpret_cast<const void *>(&k_variant_waves<F>);
+    else return nullptr;
+}
+
+template <size_t... I>
+static std::array<const void *, sizeof...(I)> variant_waves_kernels(std::index_sequence<I...>) {
+    return {variant_waves_kernel<(unsigned)I>()...};
+}
+
 template <size_t... I>
 static std::array<const void *, sizeof...(I)> plain_kernels(std::index_sequence<I...>) {
     return {plain_kernel<(unsigned)I>()...};
@@ -1424,6 +1492,22 @@ hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, 
     if (fn == nullptr) return hipErrorInvalidValue;     // excluded by argument validation
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(block), args, persistent_lds(T, block),
                            s);
+}
+
+hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &io, int block,
+                               hipStream_t s) {
+    static const auto fns = variant_waves_kernels(std::make_index_sequence<kFeatures>());
+    if (R.lanes == 0) return hipSuccess;
+    const int64_t items = R.lanes / kWave;           // (muon, 64 variants) per wavefront
+    const int64_t per_block = block / kWave;
+    const unsigned grid = (unsigned)((items + per_block - 1) / per_block);
+    Tables t = T;
+    DevRun r = R;
+    DevIO o = io;
+    void *args[] = {&t, &r, &o};
+    const void *fn = fns[feature_mask(T, R)];
+    if (fn == nullptr) return hipErrorInvalidValue;     // excluded by argument validation
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, (size_t)T.lds.bytes, s);
 }
 
 hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero,

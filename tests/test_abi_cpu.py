@@ -59,6 +59,25 @@ def test_struct_layout_matches_header():
             assert getattr(cls, field).offset == int(val), (name, field)
 
 
+def test_binding_constants_match_header():
+    """Every MT_* integer constant the Python binding mirrors has the value
+    the header defines (modes, samplers, interpolations, axes, statuses,
+    error codes)."""
+    txt = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2))
+            for m in re.finditer(r"^#define\s+(MT_\w+)\s+\(?(-?\d+)\)?", txt, re.M)}
+    checked = 0
+    for name, val in defs.items():
+        py = name if hasattr(_lib, name) else name[3:]       # MT_ST_ZMAX -> ST_ZMAX
+        if hasattr(_lib, py):
+            assert getattr(_lib, py) == val, name
+            checked += 1
+    for code, name in _lib.ERRORS.items():
+        assert defs[name] == code, name
+    assert {"MT_MODE_VARIANT_WAVES", "MT_SAMPLER_ALIAS", "MT_ST_INVALID"} <= set(defs)
+    assert checked >= 15
+
+
 def _err(L):
     return L.mt_last_error().decode()
 
