@@ -22,26 +22,60 @@ sys.path.insert(0, ROOT)
 
 METRIC = "muon-steps/sec on 1 MI355X vs CPU FP64 oracle; fwd+adjoint time per design step"
 
-# MI355X published peaks and the issue rate they imply:
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-ops/s; the
-# 157.3 TFLOP/s fp32 figure is this x 2 (FMA) x 2 (dual issue / packed).
-VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# ALU roofline.  A SIMD issues one 64-lane VALU instruction per 4 cycles at
+# the base 16-lane rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13
+# lane-operations/s, which is MI355X's published FP64 vector peak (78.6
+# TFLOP/s counting an FMA as two).  FP32 instructions issue at twice that
+# (157.3 TFLOP/s): 2 cycles per 64-lane instruction.  The peak of a step is
+# therefore that of its mix: with n_c operations of class c per step and
+# cost_c cycles per 64-lane instruction of the class, a SIMD completes
+# 64 / sum(n_c cost_c) steps per cycle.  Integer operations, the 32x32->64
+# products and the transcendentals (rsq, sin, cos) are charged the base rate
+# (no published figure; optimistic for the 64-bit products).
+CLOCK_HZ, SIMDS = 2.4e9, 256 * 4
+CLASS_CYCLES = {"f32": 2, "f64": 4, "int": 4, "mad64": 4, "trans": 4}
+VALU_BASE_LANE_OPS = SIMDS * 16 * CLOCK_HZ
 
 # Algorithmic operations of one muon step, counted from the method at the
-# granularity of single hardware operations: break
-# test 8, box lookup 6, momentum bin 2, Philox4x32-10 53 (18 32x32->64
-# products + 35 xors once the muon-constant part of rounds 1-2 is hoisted),
-# inverse CDF 7, cell split 3, jitter + azimuth 18, kick + rotation 30,
-# field 1, RK4 with FP64 accumulation 103, loop 2 -> 233 for a material step;
-# a vacuum step in zero field is 40.  The field map adds 30 (8 corner loads,
-# 21 lerps, index arithmetic); zero-field material steps replace the RK4 by
-# the straight-line update (-84).  A convex-block lookup replaces the box
-# lookup by one candidate's sign test (grid cell 9, slice 8 FMAs, 4 edge
-# products 24, sign logic 8: +43 over the cached box lookup).
-# In the variant-wave form the 64 variants of a muon share one Philox block
-# per step, so a lane's share of it is 53/64 ~ 1 operation (-52).
-OPS = {"material": 233, "vacuum": 40, "map": 30, "straight": -84, "block_lookup": 43,
-       "philox_shared": -52}
+# granularity of single hardware operations and split by class.  A material
+# step (233): break test 8 (7 FP64 compares, step cap), box lookup 6 (cached
+# box: 4 FP64 compares), momentum bin 2 (FP64), Philox4x32-10 53 (18
+# 32x32->64 products + 35 xors once the muon-constant part of rounds 1-2 is
+# hoisted), inverse CDF 7 and cell split 3 (integer), jitter + azimuth 18
+# (FP32, sin and cos), kick + rotation 30 (FP32, one rsq, the FP64 update of
+# p and its conversions), field 1, RK4 103 (FP32 stages with 4 rsq, FP64
+# accumulation and conversions), loop 2.  A vacuum step in zero field is 40.
+# The field map adds 30 (8 corner loads, 21 lerps, FP64 cell coordinates);
+# zero-field material steps replace the RK4 by the straight-line update
+# (-84).  A convex-block lookup replaces the box lookup by one candidate's
+# sign test (grid cell, slice and edge products in FP64: +43).  In the
+# variant-wave form the 64 variants of a muon share one Philox block per
+# step, so a lane's share of it is 53/64 ~ 1 operation (-52).
+OPS = {
+    "material": {"f32": 127, "f64": 31, "int": 50, "mad64": 18, "trans": 7},
+    "vacuum": {"f32": 12, "f64": 17, "int": 9, "trans": 2},
+    "map": {"f32": 15, "f64": 9, "int": 6},
+    "straight": {"f32": -80, "trans": -4},
+    "block_lookup": {"f64": 40, "int": 3},
+    "philox_shared": {"mad64": -18, "int": -34},
+}
+
+
+def _ops(*parts):
+    """Sum of operation-class vectors, each given as (count, OPS key)."""
+    out = {c: 0.0 for c in CLASS_CYCLES}
+    for count, key in parts:
+        for c, v in OPS[key].items():
+            out[c] += count * v
+    return out
+
+
+def alu_peak(ops):
+    """Lane-operations/s the SIMDs can issue for this operation mix."""
+    total = sum(ops.values())
+    cycles = sum(v * CLASS_CYCLES[c] for c, v in ops.items())
+    return total / cycles * SIMDS * CLOCK_HZ * 64
+
 
 WORKLOADS = {
     "tiny": "tiny: 1 iron box 1 m, no field, 32x64x64 histograms, 10^4 muons at 100 GeV",
@@ -75,6 +109,9 @@ def _parse():
     ap.add_argument("--cpu-muons", type=int, default=1_000_000)
     ap.add_argument("--gather-sweep", action="store_true",
                     help="only measure random-gather rates over a range of table sizes")
+    ap.add_argument("--alu-sweep", action="store_true",
+                    help="measure SIMD cycles per wave-level VALU instruction for five "
+                         "instruction kinds (libmt_gbench.so) and exit")
     ap.add_argument("--no-gather", action="store_true",
                     help="skip the gather-ceiling microbenchmark")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -130,6 +167,10 @@ def main():
         print(json.dumps({"gather_loads_per_s": rates}), flush=True)
         return
 
+    if args.alu_sweep:
+        print(json.dumps({"simd_cycles_per_wave_instruction": alu_rates(torch)}), flush=True)
+        return
+
     from paper_2512_10520_amd import api
     from paper_2512_10520_amd import workloads as W
 
@@ -177,12 +218,16 @@ def main():
     kernel = {"plain": "k_plain", "persistent": "k_persistent",
               "variant_waves": "k_variant_waves"}[mode]
     traffic = measured_traffic(kernel, args.config)
-    alg_ops = algorithmic_ops(args.config, steps_per_pass, lanes, mode)
+    mix = algorithmic_ops(args.config, steps_per_pass, lanes, mode)
+    alg_ops = sum(mix.values())
     achieved = alg_ops / (ev_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
-                "unit": "Tops/s (VALU lane-ops)", "frac": achieved / VALU_LANE_OPS_PEAK,
+    peak = alu_peak(mix)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "Tops/s (VALU lane-ops)", "frac": achieved / peak,
                 "traffic": traffic, "kernel": kernel, "kernel_ms": ev_ms,
-                "ops_per_pass": alg_ops}
+                "ops_per_pass": alg_ops,
+                "ops_mix": {c: v / steps_per_pass for c, v in mix.items()},
+                "frac_of_base_issue_rate": achieved / VALU_BASE_LANE_OPS}
     line = {"metric": METRIC, "value": value, "unit": "muon-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -244,6 +289,34 @@ def gather_rate(torch, nbytes, width, loads=256, reps=3):
     return blocks * 256 * loads / (ms * 1e-3)
 
 
+# Loop body of each k_valu kind in the gfx950 assembly: 8 instructions of the
+# kind (kind 2 also has one v_add_u32 and two v_mov_b32 per iteration).
+ALU_KINDS = {0: ("v_fmac_f32", 8), 1: ("v_add_f32", 8), 2: ("v_lshl_add_u32", 11),
+             3: ("v_fmac_f64", 8), 4: ("v_mad_u64_u32", 8)}
+
+
+def alu_rates(torch, iters=4096, clock_hz=2.4e9, simds=1024):
+    """SIMD cycles per wave-level instruction of each kind at full occupancy
+    (k_valu in libmt_gbench.so): 4 means one 64-lane instruction per 4 cycles
+    per 16-lane SIMD."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2512_10520_amd", "libmt_gbench.so"))
+    lib.mtb_valu.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint32, C.c_void_p, C.c_void_p]
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    blocks = 256 * 8
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for kind, (name, per_iter) in ALU_KINDS.items():
+        def run():
+            if lib.mtb_valu(kind, iters, blocks, 7, sink.data_ptr(), stream) != 0:
+                raise RuntimeError("VALU microbenchmark launch failed")
+        run()
+        _, ms = _time_launches(run, 3, torch)
+        wave_instr = blocks * 256 / 64 * iters * per_iter
+        out[name] = simds * clock_hz * (ms * 1e-3) / wave_instr
+    return out
+
+
 def gather_ceiling(torch, value):
     """The block path's gather roofline: its draw makes about one dependent
     table load per material step (the 8-byte guide entry; a probe of the
@@ -283,19 +356,20 @@ def per_variant_plain(api, dm, wl, scales, torch, reps=2):
 
 
 def algorithmic_ops(config, steps, lanes, mode="plain"):
-    """Algorithmic operations of one pass (see OPS).  block/scan/diff: the
+    """Algorithmic operations of one pass by class (see OPS).  block/scan/diff: the
     first step of every muon starts in vacuum before the box; tiny: zero
     field; shield: every step is counted as a material step with a map
     lookup (an upper bound: the air gaps are vacuum).  The variant-wave form
     shares the Philox block of a material step among 64 lanes."""
-    mat = OPS["material"] + (OPS["philox_shared"] if mode == "variant_waves" else 0)
+    mat = [(1, "material")] + ([(1, "philox_shared")] if mode == "variant_waves" else [])
+    scale = lambda k, parts: [(k * c, key) for c, key in parts]
     if config in ("block", "scan", "diff", "logbins"):
-        return (steps - lanes) * mat + lanes * OPS["vacuum"]
+        return _ops(*scale(steps - lanes, mat), (lanes, "vacuum"))
     if config == "tiny":
-        return (steps - lanes) * (mat + OPS["straight"]) + lanes * OPS["vacuum"]
+        return _ops(*scale(steps - lanes, mat + [(1, "straight")]), (lanes, "vacuum"))
     if config == "blocks":
-        return steps * (mat + OPS["block_lookup"])
-    return steps * (mat + OPS["map"])
+        return _ops(*scale(steps, mat + [(1, "block_lookup")]))
+    return _ops(*scale(steps, mat + [(1, "map")]))
 
 
 def measured_traffic(kernel, config):
