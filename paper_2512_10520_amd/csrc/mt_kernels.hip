@@ -1264,27 +1264,48 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
             float3 bb = make_float3(0.f, 0.f, 0.f);
             int acc_m = -1;
             double acc = 0.0;
+            // the reverse sweep loads step k-1's kick record and history
+            // while it works on step k
             next = rec[(size_t)(k1 - 1 - k0) * lanes];
+            float4 nA = make_float4(0.f, 0.f, 0.f, 0.f);
+            float2 nB = make_float2(0.f, 0.f);
+            double nx = 0.0, ny = 0.0, nz = 0.0;
+            if (!LDSH) {
+                nA = h4[(size_t)(k1 - 1 - k0) * lanes];
+                nB = h2[(size_t)(k1 - 1 - k0) * lanes];
+            }
+            if (MAP) {
+                const double *hh = hr + (size_t)(k1 - 1 - k0) * 3 * lanes;
+                nx = hh[0];
+                ny = hh[lanes];
+                nz = hh[2 * lanes];
+            }
             for (int k = k1 - 1; k >= k0; --k) {
                 const float4 cur = next;
-                if (k > k0) next = rec[(size_t)(k - 1 - k0) * lanes];
+                const float4 A = nA;
+                const float2 Bv = nB;
+                const double rx = nx, ry = ny, rz = nz;
+                if (k > k0) {
+                    next = rec[(size_t)(k - 1 - k0) * lanes];
+                    if (!LDSH) {
+                        nA = h4[(size_t)(k - 1 - k0) * lanes];
+                        nB = h2[(size_t)(k - 1 - k0) * lanes];
+                    }
+                    if (MAP) {
+                        const double *hh = hr + (size_t)(k - 1 - k0) * 3 * lanes;
+                        nx = hh[0];
+                        ny = hh[lanes];
+                        nz = hh[2 * lanes];
+                    }
+                }
                 float3 p0, a0;
                 if (LDSH) {
                     const float *h = hp + (size_t)(k - k0) * 6 * hs;
                     p0 = make_float3(h[0], h[hs], h[2 * hs]);
                     a0 = make_float3(h[3 * hs], h[4 * hs], h[5 * hs]);
                 } else {
-                    const float4 A = h4[(size_t)(k - k0) * lanes];
-                    const float2 Bv = h2[(size_t)(k - k0) * lanes];
                     p0 = make_float3(A.x, A.y, A.z);
                     a0 = make_float3(A.w, Bv.x, Bv.y);
-                }
-                double rx = 0.0, ry = 0.0, rz = 0.0;
-                if (MAP) {
-                    const double *hh = hr + (size_t)(k - k0) * 3 * lanes;
-                    rx = hh[0];
-                    ry = hh[lanes];
-                    rz = hh[2 * lanes];
                 }
                 const int vol = __float_as_int(cur.w);
                 if (vol != bvol) {
