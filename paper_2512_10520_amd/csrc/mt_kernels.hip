@@ -60,6 +60,12 @@ __device__ __forceinline__ PhiloxPrefix philox_prefix(uint32_t jlo, uint32_t jhi
     return P;
 }
 
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96), a gfx950 instruction
+// the compiler does not form from two xors by itself.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox_step(const PhiloxPrefix &P, uint32_t step, uint32_t k0,
                                              uint32_t k1) {
     // round 1: only the product with the step word varies
@@ -78,8 +84,8 @@ __device__ __forceinline__ uint4 philox_step(const PhiloxPrefix &P, uint32_t ste
     for (int r = 2; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kMulA * c0;
         const uint64_t pb = (uint64_t)kMulB * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
