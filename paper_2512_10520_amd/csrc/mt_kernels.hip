@@ -338,7 +338,8 @@ __device__ __forceinline__ int bin_of(Lane &L, const Tables &T, const Lds &S, do
 __device__ __forceinline__ int sample_cell(const DevHist &H, const Lds &S, int h, uint32_t w0) {
     const uint32_t T = S.tot[h];
     const uint32_t t = __umulhi(w0, T);
-    const uint2 e = H.guide[((size_t)h << H.gbits) | (w0 >> (32 - H.gbits))];
+    // h < 2^12 and gbits <= 16: the entry index fits in 32 bits
+    const uint2 e = H.guide[((uint32_t)h << H.gbits) | (w0 >> (32 - H.gbits))];
     int lo = (int)(e.x & 0xFFFFu);
     int hi = (int)(e.x >> 16);
     if (t < e.y) return lo;
@@ -727,7 +728,8 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         uint4 w;
         if constexpr ((F & kShared) != 0) w = w_shared;
         else w = philox_step(L.ph, (uint32_t)L.k, R.key0, R.key1);
-        const int h = mat * T.hist.n_pbin + ibin;
+        // mat < 2^12 and n_pbin <= 1024: a full-rate 24-bit multiply
+        const int h = (int)__umul24((uint32_t)mat, (uint32_t)T.hist.n_pbin) + ibin;
         if constexpr ((F & kAlias) != 0) cell = alias_cell(T.hist, h, w);
         else cell = sample_cell(T.hist, S, h, w.x);
         const int il = (int)__umulhi((uint32_t)cell, T.hist.nscat_magic);
