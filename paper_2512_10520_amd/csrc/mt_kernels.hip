@@ -227,9 +227,13 @@ __device__ __forceinline__ int find_slab(const Lds &S, int n_slab, double z, int
     return s;
 }
 
+// Branch-free: the four bounds come in two 16-byte LDS reads and the four
+// compares are combined with bitwise ands (short-circuit && would turn every
+// compare into a branch with its own dependent LDS read).
 __device__ __forceinline__ bool in_box_xy(const Lds &S, int b, double x, double y) {
-    const double *bx = S.box4 + 4 * b;
-    return bx[0] <= x && x < bx[1] && bx[2] <= y && y < bx[3];
+    const double2 *bx = reinterpret_cast<const double2 *>(S.box4 + 4 * b);
+    const double2 xr = bx[0], yr = bx[1];
+    return (xr.x <= x) & (x < xr.y) & (yr.x <= y) & (y < yr.y);
 }
 
 __device__ __forceinline__ int find_box(const Lds &S, int s, double x, double y) {
@@ -1154,6 +1158,28 @@ __device__ __forceinline__ void reverse_step(const Tables &T, const Lds &S, cons
     }
 }
 
+// One FP32 momentum of the adjoint's segment history (12 bytes, so a
+// wavefront's records of a step are one contiguous 768-byte run).
+struct Float3r {
+    float x, y, z;
+};
+
+// The stage-0 momentum of a step formed again from its FP32 pre-kick
+// momentum: the forward's kick arithmetic on (double)p0 instead of the FP64
+// state it was rounded from.  It agrees with the forward's a0 to the last bit
+// or, rarely, one unit in the last place (the FP64 state and its FP32
+// rounding differ by ~1e-8 relative), which is what the FP32 Jacobians
+// built from it need.
+__device__ __forceinline__ float3 kick_again(float3 p0, float4 rec) {
+    Lane K;
+    K.px = (double)p0.x;
+    K.py = (double)p0.y;
+    K.pz = (double)p0.z;
+    const double p2 = K.px * K.px + K.py * K.py + K.pz * K.pz;
+    kick(K, p2, rec.x, rec.y, rec.z);
+    return stage0(K);
+}
+
 // Re-run one step of a segment with its recorded kick and volume (the
 // arithmetic of advance(), so the same bits).  B caches the field of volume
 // bvol.  Returns the FP32 momentum the RK4 stages started from.
@@ -1226,9 +1252,11 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
             // kick records of the segment: one float4 per (step, lane)
             const float4 *rec = reinterpret_cast<const float4 *>(R.tape) + (size_t)k0 * lanes + g;
             L.bvol = -2;
-            // history of the segment: p0 (pre-kick) and a0 (stage-0) momenta
-            // per step, [step][6][thread] floats in LDS (LDSH), or in device
-            // memory as float4 (p0, a0.x) and float2 (a0.y, a0.z) per (step, lane)
+            // history of the segment: the pre-kick momentum p0 of every step
+            // (FP32), [step][3][thread] in LDS (LDSH) or one 12-byte record per
+            // (step, lane) in device memory.  The stage-0 momentum a0 is formed
+            // again from p0 in the reverse sweep (kick_again), which halves the
+            // history traffic the adjoint is bound by.
             float *hp;
             int64_t hs;
             if (LDSH) {
@@ -1238,34 +1266,35 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
                 hp = nullptr;
                 hs = 0;
             }
-            // device memory: float4 (p0, a0.x) and float2 (a0.y, a0.z) per (step, lane)
-            float4 *h4 = reinterpret_cast<float4 *>(scratch) + g;
-            float2 *h2 = reinterpret_cast<float2 *>(scratch + (size_t)kCkptEvery * 16 * lanes) + g;
+            Float3r *h3 = reinterpret_cast<Float3r *>(scratch) + g;
             double *hr = reinterpret_cast<double *>(
-                scratch + (size_t)kCkptEvery * 6 * sizeof(float) * lanes) + g;
-            float4 next = rec[0];
+                scratch + (size_t)kCkptEvery * sizeof(Float3r) * lanes) + g;
+            // running pointers (one 64-bit add per array and step) rather
+            // than (k - k0) * lanes products
+            const float4 *rp = rec;
+            Float3r *h3p = h3;
+            double *hrp = hr;
+            float4 next = *rp;
             for (int k = k0; k < k1; ++k) {
                 const float4 cur = next;
-                if (k + 1 < k1) next = rec[(size_t)(k + 1 - k0) * lanes];
+                rp += lanes;
+                if (k + 1 < k1) next = *rp;
                 const float p0x = (float)L.px, p0y = (float)L.py, p0z = (float)L.pz;
                 if (MAP) {
-                    double *hh = hr + (size_t)(k - k0) * 3 * lanes;
-                    hh[0] = L.x;
-                    hh[lanes] = L.y;
-                    hh[2 * lanes] = L.z;
+                    hrp[0] = L.x;
+                    hrp[lanes] = L.y;
+                    hrp[2 * lanes] = L.z;
+                    hrp += 3 * lanes;
                 }
-                const float3 a0 = replay_step<MAP>(L, T, S, R, sc, var, cur);
+                replay_step<MAP>(L, T, S, R, sc, var, cur);
                 if (LDSH) {
-                    float *h = hp + (size_t)(k - k0) * 6 * hs;
+                    float *h = hp + (size_t)(k - k0) * 3 * hs;
                     h[0] = p0x;
                     h[hs] = p0y;
                     h[2 * hs] = p0z;
-                    h[3 * hs] = a0.x;
-                    h[4 * hs] = a0.y;
-                    h[5 * hs] = a0.z;
                 } else {
-                    h4[(size_t)(k - k0) * lanes] = make_float4(p0x, p0y, p0z, a0.x);
-                    h2[(size_t)(k - k0) * lanes] = make_float2(a0.y, a0.z);
+                    *h3p = Float3r{p0x, p0y, p0z};
+                    h3p += lanes;
                 }
             }
             int bvol = -2;
@@ -1274,48 +1303,45 @@ __global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, c
             double acc = 0.0;
             // the reverse sweep loads step k-1's kick record and history
             // while it works on step k
-            next = rec[(size_t)(k1 - 1 - k0) * lanes];
-            float4 nA = make_float4(0.f, 0.f, 0.f, 0.f);
-            float2 nB = make_float2(0.f, 0.f);
+            rp -= lanes;                 // step k1 - 1
+            h3p -= lanes;
+            hrp -= 3 * lanes;
+            next = *rp;
+            Float3r nP{0.f, 0.f, 0.f};
             double nx = 0.0, ny = 0.0, nz = 0.0;
-            if (!LDSH) {
-                nA = h4[(size_t)(k1 - 1 - k0) * lanes];
-                nB = h2[(size_t)(k1 - 1 - k0) * lanes];
-            }
+            if (!LDSH) nP = *h3p;
             if (MAP) {
-                const double *hh = hr + (size_t)(k1 - 1 - k0) * 3 * lanes;
-                nx = hh[0];
-                ny = hh[lanes];
-                nz = hh[2 * lanes];
+                nx = hrp[0];
+                ny = hrp[lanes];
+                nz = hrp[2 * lanes];
             }
             for (int k = k1 - 1; k >= k0; --k) {
                 const float4 cur = next;
-                const float4 A = nA;
-                const float2 Bv = nB;
+                const Float3r P = nP;
                 const double rx = nx, ry = ny, rz = nz;
                 if (k > k0) {
-                    next = rec[(size_t)(k - 1 - k0) * lanes];
+                    rp -= lanes;
+                    next = *rp;
                     if (!LDSH) {
-                        nA = h4[(size_t)(k - 1 - k0) * lanes];
-                        nB = h2[(size_t)(k - 1 - k0) * lanes];
+                        h3p -= lanes;
+                        nP = *h3p;
                     }
                     if (MAP) {
-                        const double *hh = hr + (size_t)(k - 1 - k0) * 3 * lanes;
-                        nx = hh[0];
-                        ny = hh[lanes];
-                        nz = hh[2 * lanes];
+                        hrp -= 3 * lanes;
+                        nx = hrp[0];
+                        ny = hrp[lanes];
+                        nz = hrp[2 * lanes];
                     }
                 }
-                float3 p0, a0;
+                float3 p0;
                 if (LDSH) {
-                    const float *h = hp + (size_t)(k - k0) * 6 * hs;
+                    const float *h = hp + (size_t)(k - k0) * 3 * hs;
                     p0 = make_float3(h[0], h[hs], h[2 * hs]);
-                    a0 = make_float3(h[3 * hs], h[4 * hs], h[5 * hs]);
                 } else {
-                    p0 = make_float3(A.x, A.y, A.z);
-                    a0 = make_float3(A.w, Bv.x, Bv.y);
+                    p0 = make_float3(P.x, P.y, P.z);
                 }
                 const int vol = __float_as_int(cur.w);
+                const float3 a0 = (vol >= 0 && S.mat[vol] >= 0) ? kick_again(p0, cur) : p0;
                 if (vol != bvol) {
                     bb = box_field(T, S, R, vol, var);
                     bvol = vol;
@@ -1557,7 +1583,7 @@ static bool adjoint_lds_history(const Tables &T) {
 }
 
 int64_t adjoint_scratch_bytes(const Tables &T, int64_t lanes) {
-    return (int64_t)kCkptEvery * (6 * sizeof(float) + 3 * sizeof(double)) * lanes;
+    return (int64_t)kCkptEvery * (sizeof(Float3r) + 3 * sizeof(double)) * lanes;
 }
 
 hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
@@ -1568,7 +1594,7 @@ hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
     const bool map = T.field.map != nullptr;
     const bool ldsh = adjoint_lds_history(T);
     size_t shm = (size_t)((T.lds.bytes + 15) & ~15) + (size_t)T.geom.n_mag * block * sizeof(double);
-    if (ldsh) shm += (size_t)kCkptEvery * 6 * block * sizeof(float);   // p0 and a0 per step
+    if (ldsh) shm += (size_t)kCkptEvery * 3 * block * sizeof(float);   // p0 per step
     char *sc = reinterpret_cast<char *>(scratch);
     if (map)
         hipLaunchKernelGGL((k_adjoint<true, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);
