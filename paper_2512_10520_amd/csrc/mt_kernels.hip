@@ -711,17 +711,20 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
     constexpr bool MAP = (F & kMap) != 0, TAPE = (F & kTape) != 0, TRACE = (F & kTrace) != 0;
     const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
     // Break test in the order p_min, z_max, x_max, y_max, step cap (the first
-    // that holds decides the status).
-    int st = (L.k >= R.max_steps) ? MT_ST_MAXSTEPS : MT_ST_RUNNING;
-    st = (fabs(L.y) >= T.geom.y_max) ? MT_ST_YMAX : st;
-    st = (fabs(L.x) >= T.geom.x_max) ? MT_ST_XMAX : st;
-    st = (L.z >= T.geom.z_max) ? MT_ST_ZMAX : st;
-    st = (p2 < R.pmin2) ? MT_ST_PMIN : st;
+    // that holds decides the status).  The five compares are or-ed as masks;
+    // the status is picked only on the rare step that stops.
+    const bool c_pmin = p2 < R.pmin2, c_z = L.z >= T.geom.z_max;
+    const bool c_x = fabs(L.x) >= T.geom.x_max, c_y = fabs(L.y) >= T.geom.y_max;
+    const bool c_k = L.k >= R.max_steps;
     int vol;
     if constexpr ((F & kPoly) != 0) vol = locate_block(L, T, S);
     else vol = locate(L, T, S);
-    if (st != MT_ST_RUNNING) {       // the muon stops here; vol is its final volume
-        L.status = st;
+    if (c_pmin | c_z | c_x | c_y | c_k) {   // the muon stops here; vol is its final volume
+        L.status = c_pmin ? MT_ST_PMIN
+                 : c_z    ? MT_ST_ZMAX
+                 : c_x    ? MT_ST_XMAX
+                 : c_y    ? MT_ST_YMAX
+                          : MT_ST_MAXSTEPS;
         return false;
     }
     const int mat = vol >= 0 ? S.mat[vol] : -1;
