@@ -1226,8 +1226,11 @@ __device__ __forceinline__ float3 replay_step(Lane &L, const Tables &T, const Ld
 // The segment's start momenta are kept either in LDS (LDSH) or in a per-lane
 // scratch area in device memory; with a field map the start positions are
 // needed too and always go to the scratch area.
+// Without a map the kernel needs 103 VGPRs (4 waves/SIMD); asking for 5 waves
+// spills a few values kept across the segment loops and runs 3 % faster.
 template <bool MAP, bool LDSH>
-__global__ void __launch_bounds__(256) k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP ? 1 : 5)))
+k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
                                                  double *g_in, double *gs_lane, char *scratch) {
     extern __shared__ __align__(16) char smem[];
     const Lds S = stage_tables<false>(smem, T);
