@@ -915,11 +915,12 @@ __device__ __forceinline__ void unpack_rec(Lane &L, const MoveRec &m, int32_t k,
     L.e2hi = -INFINITY;
 }
 
-// Without a map the compaction state leaves the kernel a few registers above
-// the 96 of 5 waves/SIMD; asking for 5 waves spills three rarely used values
-// and runs the block and scan workloads 7-8 % faster than 4 waves.
+// Without a map, convex blocks or per-stage fields the compaction state leaves
+// the kernel a few registers above the 96 of 5 waves/SIMD; asking for 5 waves spills three
+// rarely used values and runs the block and scan workloads 7-8 % faster than
+// 4 waves.
 template <unsigned F>     // F never holds kTape
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((F & kMap) ? 1 : 5)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((F & (kMap | kPoly | kStages)) ? 1 : 5)))
 k_persistent(Tables T, DevRun R, DevIO io, int compact,
                                                      unsigned long long *queue) {
     extern __shared__ __align__(16) char smem[];
