@@ -983,8 +983,10 @@ k_persistent(Tables T, DevRun R, DevIO io, int compact,
 // Variant-wave form (field variants of the same muons).  All variants of
 // muon j draw the same random words at step k, so a wavefront that holds 64
 // variants of one muon needs one Philox block per step, not 64: every 64
-// steps lane l forms the block of step k + l, and at step k every lane takes
-// the four words from lane k mod 64 (v_readlane).  The lanes of such a
+// steps lane l forms the block of step k + l into the wavefront's 1 KB of
+// LDS, and at step k every lane reads entry k mod 64 (one address for the
+// whole wavefront, so the LDS broadcasts it; the wavefront's own LDS writes
+// and reads are ordered, so no barrier is needed).  The lanes of such a
 // wavefront step in lockstep (all start at step 0, and each pass of the loop
 // is one step for every lane still running), which is what makes the shared
 // block the right one; a lane whose muon has stopped still forms its block
@@ -1007,22 +1009,22 @@ __global__ void __launch_bounds__(1024) k_variant_waves(Tables T, DevRun R, DevI
     const int64_t j = it / groups;
     const int64_t var = (it - j * groups) * kWave + lane;
     Lane L;
-    load_lane_at(L, j, var, var * n + j, io, R);
+    load_lane_at(L, j, var, 0, io, R);           // output slot formed after the loop
     const PhiloxPrefix P =
         philox_prefix((uint32_t)j, (uint32_t)((uint64_t)j >> 32), R.key0, R.key1);
     bool running = L.status == MT_ST_RUNNING;
-    uint4 blk = make_uint4(0u, 0u, 0u, 0u);
+    // the wavefront's 64 Philox blocks (one per step of the next 64), 1 KB of LDS
+    uint4 *wblk = reinterpret_cast<uint4 *>(smem + ((T.lds.bytes + 15) & ~15)) +
+                  (threadIdx.x & ~(unsigned)(kWave - 1));
     for (int k = 0; __ballot(running) != 0; ++k) {
         const int sl = k & (kWave - 1);
-        if (sl == 0) blk = philox_step(P, (uint32_t)(k + lane), R.key0, R.key1);
+        if (sl == 0) wblk[lane] = philox_step(P, (uint32_t)(k + lane), R.key0, R.key1);
         if (running) {
-            const uint4 w = make_uint4((uint32_t)__builtin_amdgcn_readlane((int)blk.x, sl),
-                                       (uint32_t)__builtin_amdgcn_readlane((int)blk.y, sl),
-                                       (uint32_t)__builtin_amdgcn_readlane((int)blk.z, sl),
-                                       (uint32_t)__builtin_amdgcn_readlane((int)blk.w, sl));
+            const uint4 w = wblk[sl];             // one address for the wavefront: a broadcast
             running = advance<F | kShared>(L, T, S, R, sc, w);
         }
     }
+    L.g = (int64_t)L.var * n + j;
     store_lane(L, T, S, io);
 }
 
@@ -1583,7 +1585,8 @@ hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &i
     void *args[] = {&t, &r, &o};
     const void *fn = fns[feature_mask(T, R)];
     if (fn == nullptr) return hipErrorInvalidValue;     // excluded by argument validation
-    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, (size_t)T.lds.bytes, s);
+    const size_t lds = (size_t)((T.lds.bytes + 15) & ~15) + (size_t)block * sizeof(uint4);
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
 }
 
 hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero,
