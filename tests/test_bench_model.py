@@ -1,0 +1,51 @@
+"""Host checks of bench.py's bookkeeping (no GPU): the operation-class model
+behind the ALU roofline, the mix-weighted peak, and the one-GPU contract."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_operation_totals():
+    """The class split of each step part adds up to its documented total."""
+    totals = {k: sum(v.values()) for k, v in bench.OPS.items()}
+    assert totals == {"material": 233, "vacuum": 40, "map": 30, "straight": -84,
+                      "block_lookup": 43, "philox_shared": -52}
+    assert set().union(*(v.keys() for v in bench.OPS.values())) <= set(bench.CLASS_CYCLES)
+
+
+def test_mix_peak_limits():
+    """A pure-FP32 mix issues at twice the base rate, any other pure class at
+    the base rate, and a mix lies between."""
+    base = bench.VALU_BASE_LANE_OPS
+    assert bench.alu_peak({"f32": 10.0}) == pytest.approx(2 * base)
+    for c in ("f64", "int", "mad64", "trans"):
+        assert bench.alu_peak({c: 7.0}) == pytest.approx(base)
+    mix = bench._ops((1, "material"))
+    assert base < bench.alu_peak(mix) < 2 * base
+    # 127 FP32 ops at 2 cycles and 106 others at 4: 233 ops in 466 cycle-units
+    assert bench.alu_peak(mix) == pytest.approx(233 / (127 * 2 + 106 * 4) * 4 * base)
+
+
+def test_algorithmic_ops_per_workload():
+    steps, lanes = 1000, 10
+    blk = bench.algorithmic_ops("block", steps, lanes)
+    assert sum(blk.values()) == (steps - lanes) * 233 + lanes * 40
+    vw = bench.algorithmic_ops("scan", steps, lanes, "variant_waves")
+    assert sum(vw.values()) == (steps - lanes) * (233 - 52) + lanes * 40
+    assert sum(bench.algorithmic_ops("shield", steps, lanes).values()) == steps * (233 + 30)
+    assert sum(bench.algorithmic_ops("blocks", steps, lanes).values()) == steps * (233 + 43)
+    tiny = bench.algorithmic_ops("tiny", steps, lanes)
+    assert sum(tiny.values()) == (steps - lanes) * (233 - 84) + lanes * 40
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
