@@ -215,3 +215,16 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
         for k in ref:
             assert np.array_equal(getattr(out, k).cpu().numpy(), ref[k]), (rep, k)
+
+
+@pytest.mark.parametrize("name,kw", [("block", {}), ("logbins", {}),
+                                     ("scan", {"n_variants": 4})])
+def test_persistent_with_trace_matches_plain(name, kw):
+    """The persistent kernels of the map-free workloads (asked for 5
+    waves/SIMD, a few values spilled) give the plain launch's bits, per-step
+    traces included."""
+    wl = W.make_workload(name, n_muons=6000, **kw)
+    a = gpu_run(wl, mode="plain", trace_steps=300, n_trace=400)
+    b = gpu_run(wl, mode="persistent", trace_steps=300, n_trace=400)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), (name, k)
