@@ -61,10 +61,10 @@ extern "C" {
 /* ---- launch forms ------------------------------------------------------ */
 #define MT_MODE_PLAIN       0    /* one lane per muon until it stops */
 #define MT_MODE_PERSISTENT  1    /* resident grid, atomic work queue, compaction */
-#define MT_MODE_VARIANT_WAVES 2  /* each wavefront transports 64 variants of one muon, which
-                                    share the muon's random stream: one Philox block per lane
-                                    per 64 steps instead of one per step; needs
-                                    n_variants % 64 == 0, no trace */
+#define MT_MODE_VARIANT_WAVES 2  /* G lanes of a wavefront hold G variants of one muon and
+                                    share its random stream, G = the largest power of two
+                                    dividing n_variants, at most 64: one Philox block per
+                                    lane per G steps instead of one per step; no trace */
 
 /* ---- samplers of the histogram cell ------------------------------------ */
 #define MT_SAMPLER_CDF      0    /* exact inverse CDF over integer counts */

@@ -189,9 +189,6 @@ int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *
     if (p->mode != MT_MODE_PLAIN && p->mode != MT_MODE_PERSISTENT &&
         p->mode != MT_MODE_VARIANT_WAVES)
         return fail(MT_ERR_INVALID_ARG, "unknown mode %d", p->mode);
-    if (p->mode == MT_MODE_VARIANT_WAVES && p->n_variants % mt::kWave != 0)
-        return fail(MT_ERR_INVALID_ARG, "MT_MODE_VARIANT_WAVES needs n_variants %% %d == 0 "
-                                        "(got %d)", mt::kWave, p->n_variants);
     if (p->mode == MT_MODE_VARIANT_WAVES && p->n_trace > 0 && p->trace_steps > 0)
         return fail(MT_ERR_INVALID_ARG, "MT_MODE_VARIANT_WAVES does not record traces");
     if (p->block != 0 && (p->block < 64 || p->block > 1024 || p->block % 64 != 0))
@@ -250,6 +247,10 @@ int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *
     R.sampler = p->sampler;
     R.interp = p->interp;
     R.stage_field = p->stage_field;
+    // lanes sharing a random stream in the variant-wave form: the largest
+    // power of two dividing n_variants, at most one wavefront
+    R.share_shift = 0;
+    while (R.share_shift < 6 && p->n_variants % (2 << R.share_shift) == 0) ++R.share_shift;
     R.pmin2 = p->p_min * p->p_min;
     R.max_steps = p->max_steps;
     R.key0 = (uint32_t)p->seed;

@@ -75,6 +75,7 @@ struct DevRun {
     int32_t sampler;             // MT_SAMPLER_*
     int32_t interp;              // MT_INTERP_*
     int32_t stage_field;         // 0: field held from the step start, 1: at every RK4 stage
+    int32_t share_shift;         // variant-wave form: log2 of the lanes sharing a random stream
     double pmin2;
     int32_t max_steps;
     uint32_t key0, key1;

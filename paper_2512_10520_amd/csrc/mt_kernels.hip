@@ -981,18 +981,21 @@ k_persistent(Tables T, DevRun R, DevIO io, int compact,
 
 // ---------------------------------------------------------------------------
 // Variant-wave form (field variants of the same muons).  All variants of
-// muon j draw the same random words at step k, so a wavefront that holds 64
-// variants of one muon needs one Philox block per step, not 64: every 64
-// steps lane l forms the block of step k + l into the wavefront's 1 KB of
-// LDS, and at step k every lane reads entry k mod 64 (one address for the
-// whole wavefront, so the LDS broadcasts it; the wavefront's own LDS writes
-// and reads are ordered, so no barrier is needed).  The lanes of such a
-// wavefront step in lockstep (all start at step 0, and each pass of the loop
-// is one step for every lane still running), which is what makes the shared
-// block the right one; a lane whose muon has stopped still forms its block
-// for the others.  Wavefront w of the grid takes item w = (muon j, group of
-// 64 variants).  Results are bit-identical to the other forms (same words,
-// same arithmetic, same output slots).
+// muon j draw the same random words at step k, so G lanes that hold G
+// variants of one muon need one Philox block per step, not G.  G is the
+// largest power of two that divides the variant count, at most 64 (the
+// design scan's 64 variants give G = 64: a whole wavefront per muon).  Every
+// G steps lane l forms the block of step k + (l mod G) for its group's muon
+// into the wavefront's 1 KB of LDS, and at step k every lane reads its
+// group's entry k mod G (one address per group, which the LDS broadcasts;
+// the wavefront's own LDS writes and reads are ordered, so no barrier is
+// needed).  The lanes of a wavefront step in lockstep (all start at step 0,
+// and each pass of the loop is one step for every lane still running), which
+// is what makes the shared block the right one; a lane whose muon has
+// stopped still forms its block for the others.  Wavefront w takes the
+// 64 / G consecutive (muon, group of G variants) units from w 64 / G on.
+// Results are bit-identical to the other forms (same words, same arithmetic,
+// same output slots).
 // ---------------------------------------------------------------------------
 template <unsigned F>     // F holds neither kTape nor kTrace
 __global__ void __launch_bounds__(1024) k_variant_waves(Tables T, DevRun R, DevIO io) {
@@ -1000,32 +1003,44 @@ __global__ void __launch_bounds__(1024) k_variant_waves(Tables T, DevRun R, DevI
     const Lds S = stage_tables<(F & kPoly) != 0>(smem, T);
     const StepConst sc = step_const(R);
     const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int gs = R.share_shift, gm = (1 << gs) - 1;   // G = 2^gs lanes per muon
     const int64_t n = R.n;
-    const int64_t groups = R.lanes / n / kWave;      // groups of 64 variants per muon
-    // the item index is the same for the whole wavefront
-    const int64_t it = (int64_t)blockIdx.x * (blockDim.x / kWave) +
-                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    if (it >= n * groups) return;
-    const int64_t j = it / groups;
-    const int64_t var = (it - j * groups) * kWave + lane;
+    const int64_t vgroups = (R.lanes / n) >> gs;       // groups of G variants per muon
+    const int64_t units = n * vgroups;
+    // the first unit of the wavefront is the same for all its lanes
+    const int64_t first = ((int64_t)blockIdx.x * (blockDim.x / kWave) +
+                           __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave))) *
+                          (kWave >> gs);
+    if (first >= units) return;
+    const int64_t unit = first + (lane >> gs);
+    const bool valid = unit < units;                   // the last wavefront may be ragged
+    const int64_t j = valid ? unit / vgroups : 0;
+    const int64_t var = valid ? (unit - j * vgroups) * (gm + 1) + (lane & gm) : 0;
     Lane L;
-    load_lane_at(L, j, var, 0, io, R);           // output slot formed after the loop
+    bool running = false;
+    if (valid) {
+        load_lane_at(L, j, var, 0, io, R);         // output slot formed after the loop
+        running = L.status == MT_ST_RUNNING;
+    }
     const PhiloxPrefix P =
         philox_prefix((uint32_t)j, (uint32_t)((uint64_t)j >> 32), R.key0, R.key1);
-    bool running = L.status == MT_ST_RUNNING;
-    // the wavefront's 64 Philox blocks (one per step of the next 64), 1 KB of LDS
+    // the wavefront's Philox blocks: lane l holds its group's block of step
+    // k0 + (l mod G), 1 KB of LDS per wavefront
     uint4 *wblk = reinterpret_cast<uint4 *>(smem + ((T.lds.bytes + 15) & ~15)) +
                   (threadIdx.x & ~(unsigned)(kWave - 1));
+    const int base = lane & ~gm;
     for (int k = 0; __ballot(running) != 0; ++k) {
-        const int sl = k & (kWave - 1);
-        if (sl == 0) wblk[lane] = philox_step(P, (uint32_t)(k + lane), R.key0, R.key1);
+        const int sl = k & gm;
+        if (sl == 0) wblk[lane] = philox_step(P, (uint32_t)(k + (lane & gm)), R.key0, R.key1);
         if (running) {
-            const uint4 w = wblk[sl];             // one address for the wavefront: a broadcast
+            const uint4 w = wblk[base + sl];      // one address per group: a broadcast
             running = advance<F | kShared>(L, T, S, R, sc, w);
         }
     }
-    L.g = (int64_t)L.var * n + j;
-    store_lane(L, T, S, io);
+    if (valid) {
+        L.g = (int64_t)L.var * n + j;
+        store_lane(L, T, S, io);
+    }
 }
 
 __global__ void k_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero) {
@@ -1576,9 +1591,12 @@ hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &i
                                hipStream_t s) {
     static const auto fns = variant_waves_kernels(std::make_index_sequence<kFeatures>());
     if (R.lanes == 0) return hipSuccess;
-    const int64_t items = R.lanes / kWave;           // (muon, 64 variants) per wavefront
+    // (muon, group of G variants) units, 64 / G per wavefront
+    const int64_t units = R.lanes >> R.share_shift;
+    const int64_t per_wave = kWave >> R.share_shift;
+    const int64_t waves = (units + per_wave - 1) / per_wave;
     const int64_t per_block = block / kWave;
-    const unsigned grid = (unsigned)((items + per_block - 1) / per_block);
+    const unsigned grid = (unsigned)((waves + per_block - 1) / per_block);
     Tables t = T;
     DevRun r = R;
     DevIO o = io;
