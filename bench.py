@@ -49,16 +49,25 @@ VALU_BASE_LANE_OPS = SIMDS * 16 * CLOCK_HZ
 # zero-field material steps replace the RK4 by the straight-line update
 # (-84).  A convex-block lookup replaces the box lookup by one candidate's
 # sign test (grid cell, slice and edge products in FP64: +43).  In the
-# variant-wave form the 64 variants of a muon share one Philox block per
-# step, so a lane's share of it is 53/64 ~ 1 operation (-52).
+# variant-wave form G lanes holding variants of one muon share one Philox
+# block per step, so a lane's share of its 53 operations is 53 / G.
 OPS = {
     "material": {"f32": 127, "f64": 31, "int": 50, "mad64": 18, "trans": 7},
     "vacuum": {"f32": 12, "f64": 17, "int": 9, "trans": 2},
     "map": {"f32": 15, "f64": 9, "int": 6},
     "straight": {"f32": -80, "trans": -4},
     "block_lookup": {"f64": 40, "int": 3},
-    "philox_shared": {"mad64": -18, "int": -34},
 }
+PHILOX = {"mad64": 18, "int": 35}        # the Philox part of a material step
+
+
+def share_group(n_variants):
+    """Lanes sharing a random stream in the variant-wave form: the largest
+    power of two dividing the variant count, at most 64."""
+    g = 1
+    while g < 64 and n_variants % (2 * g) == 0:
+        g *= 2
+    return g
 
 
 def _ops(*parts):
@@ -218,7 +227,7 @@ def main():
     kernel = {"plain": "k_plain", "persistent": "k_persistent",
               "variant_waves": "k_variant_waves"}[mode]
     traffic = measured_traffic(kernel, args.config)
-    mix = algorithmic_ops(args.config, steps_per_pass, lanes, mode)
+    mix = algorithmic_ops(args.config, steps_per_pass, lanes, mode, wl.run.n_variants)
     alg_ops = sum(mix.values())
     achieved = alg_ops / (ev_ms * 1e-3)
     peak = alu_peak(mix)
@@ -355,21 +364,31 @@ def per_variant_plain(api, dm, wl, scales, torch, reps=2):
     return ms
 
 
-def algorithmic_ops(config, steps, lanes, mode="plain"):
+def algorithmic_ops(config, steps, lanes, mode="plain", n_variants=64):
     """Algorithmic operations of one pass by class (see OPS).  block/scan/diff: the
     first step of every muon starts in vacuum before the box; tiny: zero
     field; shield: every step is counted as a material step with a map
     lookup (an upper bound: the air gaps are vacuum).  The variant-wave form
-    shares the Philox block of a material step among 64 lanes."""
-    mat = [(1, "material")] + ([(1, "philox_shared")] if mode == "variant_waves" else [])
+    shares the Philox block of a material step among share_group(n_variants)
+    lanes."""
     scale = lambda k, parts: [(k * c, key) for c, key in parts]
     if config in ("block", "scan", "diff", "logbins"):
-        return _ops(*scale(steps - lanes, mat), (lanes, "vacuum"))
-    if config == "tiny":
-        return _ops(*scale(steps - lanes, mat + [(1, "straight")]), (lanes, "vacuum"))
-    if config == "blocks":
-        return _ops(*scale(steps, mat + [(1, "block_lookup")]))
-    return _ops(*scale(steps, mat + [(1, "map")]))
+        n_mat = steps - lanes
+        out = _ops(*scale(n_mat, [(1, "material")]), (lanes, "vacuum"))
+    elif config == "tiny":
+        n_mat = steps - lanes
+        out = _ops(*scale(n_mat, [(1, "material"), (1, "straight")]), (lanes, "vacuum"))
+    elif config == "blocks":
+        n_mat = steps
+        out = _ops(*scale(steps, [(1, "material"), (1, "block_lookup")]))
+    else:
+        n_mat = steps
+        out = _ops(*scale(steps, [(1, "material"), (1, "map")]))
+    if mode == "variant_waves":
+        keep = 1.0 / share_group(n_variants)
+        for c, v in PHILOX.items():
+            out[c] -= n_mat * v * (1.0 - keep)
+    return out
 
 
 def measured_traffic(kernel, config):

@@ -15,7 +15,9 @@ def test_operation_totals():
     """The class split of each step part adds up to its documented total."""
     totals = {k: sum(v.values()) for k, v in bench.OPS.items()}
     assert totals == {"material": 233, "vacuum": 40, "map": 30, "straight": -84,
-                      "block_lookup": 43, "philox_shared": -52}
+                      "block_lookup": 43}
+    assert sum(bench.PHILOX.values()) == 53
+    assert all(bench.OPS["material"][c] >= v for c, v in bench.PHILOX.items())
     assert set().union(*(v.keys() for v in bench.OPS.values())) <= set(bench.CLASS_CYCLES)
 
 
@@ -36,8 +38,11 @@ def test_algorithmic_ops_per_workload():
     steps, lanes = 1000, 10
     blk = bench.algorithmic_ops("block", steps, lanes)
     assert sum(blk.values()) == (steps - lanes) * 233 + lanes * 40
-    vw = bench.algorithmic_ops("scan", steps, lanes, "variant_waves")
-    assert sum(vw.values()) == (steps - lanes) * (233 - 52) + lanes * 40
+    vw = bench.algorithmic_ops("scan", steps, lanes, "variant_waves", 64)
+    assert sum(vw.values()) == pytest.approx((steps - lanes) * (233 - 53 + 53 / 64) + lanes * 40)
+    vw8 = bench.algorithmic_ops("scan", steps, lanes, "variant_waves", 24)   # G = 8
+    assert sum(vw8.values()) == pytest.approx((steps - lanes) * (233 - 53 + 53 / 8) + lanes * 40)
+    assert [bench.share_group(v) for v in (1, 3, 8, 12, 64, 96, 128)] == [1, 1, 8, 4, 64, 32, 64]
     assert sum(bench.algorithmic_ops("shield", steps, lanes).values()) == steps * (233 + 30)
     assert sum(bench.algorithmic_ops("blocks", steps, lanes).values()) == steps * (233 + 43)
     tiny = bench.algorithmic_ops("tiny", steps, lanes)
