@@ -110,7 +110,7 @@ hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, 
                              int grid, int compact_every, unsigned long long *queue,
                              hipStream_t s);
 int persistent_blocks_per_cu(const Tables &T, int block);
-// Variant-wave form: wavefront w transports 64 variants of one muon (lanes % 64 == 0).
+// Variant-wave form: groups of 2^R.share_shift lanes hold variants of one muon.
 hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &io, int block,
                                hipStream_t s);
 hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n_zero,
