@@ -441,10 +441,40 @@ def design_step(api, W, torch, reps=3):
             ck_ms.append(e[1].elapsed_time(e[2]))
             bwd_ms.append(e[2].elapsed_time(e[3]))
     f, c, b = (float(np.median(v)) for v in (fwd_ms, ck_ms, bwd_ms))
+    steps = int(plain.n_steps.to(torch.int64).sum().item())
+    # The adjoint kernel alone: without a scale gradient the backward call
+    # launches nothing else.
+    fwd = api.propagate(dm, spec, scales=scales, ckpt=True)
+    g_out = torch.ones((6, len(dm)), dtype=torch.float64, device="cuda")
+    api.propagate_backward(dm, spec, fwd, g_out, scales=scales)
+    _, adj_ms = _time_launches(lambda: api.propagate_backward(dm, spec, fwd, g_out, scales=scales),
+                               reps, torch)
+    n_mag = int(np.asarray(wl.run.scales).shape[-1])
+    alg = adjoint_bytes(steps, len(dm), n_mag)
+    achieved = alg / (adj_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_adjoint", "diff"),
+                "kernel": "k_adjoint", "kernel_ms": adj_ms, "bytes_per_pass": alg}
     return {"workload": "diff: 8 iron slabs at unit scale, 10^6 muons, loss at z = 30 m",
+            "muon_steps_per_pass": steps,
             "forward_ms": f, "forward_ckpt_ms": c, "backward_ms": b,
             "design_step_ms": c + b, "backward_over_forward": b / f,
+            "adjoint_roofline": roofline,
             "grad_scales": sc.grad.cpu().tolist()}
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def adjoint_bytes(steps, lanes, n_mag):
+    """Device-memory bytes the checkpoint-and-replay adjoint has to move.  Per
+    muon-step: the 16-byte kick record read twice (segment replay and reverse
+    sweep), the 12-byte pre-kick momentum written in the replay and read in
+    the reverse sweep, and a 48-byte FP64 checkpoint read once per 16 steps.
+    Per lane: the output gradient read and the input gradient written (48
+    bytes each), step count, status and charge (16), and one FP64 scale
+    gradient per magnet written."""
+    return steps * (2 * 16 + 2 * 12 + 48 / 16) + lanes * (48 + 48 + 16 + 8 * n_mag)
 
 
 def cpu_baseline(wl, n_muons):

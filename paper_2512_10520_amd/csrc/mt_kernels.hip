@@ -1258,8 +1258,9 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
     double *sgs = reinterpret_cast<double *>(smem + ((T.lds.bytes + 15) & ~15)) + threadIdx.x;
     float *hist = reinterpret_cast<float *>(smem + ((T.lds.bytes + 15) & ~15) +
                                             (size_t)n_mag * bd * sizeof(double)) + threadIdx.x;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= R.lanes) return;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = g0 < R.lanes;
+    const int64_t g = live ? g0 : R.lanes - 1;   // lanes past the end idle below
     const int64_t lanes = R.lanes;
     for (int m = 0; m < n_mag; ++m) sgs[m * bd] = 0.0;
     double lr[3], lp[3];
@@ -1274,8 +1275,21 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
     const float q = (float)io.q[g - (int64_t)var * R.n];
     const float kq = (float)kKappa * q;
 
-    if (status != MT_ST_INVALID && ns > 0) {
-        for (int seg = (ns - 1) / kCkptEvery; seg >= 0; --seg) {
+    // The lanes of a wavefront walk the checkpoint segments together, from
+    // the wavefront's last one down: a lane whose own last segment is lower
+    // waits until the walk reaches it.  Lanes then read the same tape and
+    // checkpoint rows at the same time (one cache line per 8 lanes), where
+    // each lane starting at its own last segment would split a wavefront's
+    // reads over several rows.  Every lane's arithmetic and its order are
+    // unchanged.
+    const int top = (live && status != MT_ST_INVALID && ns > 0) ? (ns - 1) / kCkptEvery : -1;
+    int wtop = top;
+    for (int o = kWave / 2; o > 0; o >>= 1) wtop = max(wtop, __shfl_xor(wtop, o));
+    wtop = __builtin_amdgcn_readfirstlane(wtop);
+
+    {
+        for (int seg = wtop; seg >= 0; --seg) {
+            if (seg > top) continue;
             const int k0 = seg * kCkptEvery;
             const int k1 = min(k0 + kCkptEvery, ns);
             Lane L;
@@ -1399,6 +1413,7 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
             if (acc_m >= 0) sgs[acc_m * bd] += acc;
         }
     }
+    if (!live) return;
     for (int a = 0; a < 3; ++a) {
         g_in[a * lanes + g] = lr[a];
         g_in[(3 + a) * lanes + g] = lp[a];
