@@ -129,3 +129,33 @@ def test_adjoint_with_field_map_inputs(torch):
         scale = np.abs(r).max()
         bad = np.abs(gg - r) > 5e-3 * np.abs(r) + 1e-3 * scale
         assert not bad.any(), (a, np.flatnonzero(bad)[:5], gg[bad][:5], r[bad][:5])
+
+
+@pytest.mark.parametrize("name", ["diff", "block"])
+def test_adjoint_lane_independent_of_its_wavefront(torch, name):
+    """The lanes of a wavefront walk their checkpoint segments together, each
+    waiting until the walk reaches its own last segment.  A muon's gradient
+    must not depend on which muons share its wavefront.  Random numbers are
+    keyed by a muon's position in the batch, so every third position keeps
+    its muon while the muons at all other positions are permuted among
+    themselves: the kept muons' input gradients must equal those of the
+    index-ordered batch bit for bit.  A prefix of 77 muons (one full and one
+    partial wavefront) must likewise reproduce the first 77 gradients.  The
+    block workload's power-law momenta give the lanes of a wavefront very
+    different segment counts."""
+    n = 3000
+    wl = W.make_workload(name, n_muons=n, n_fill=200_000)
+    full, _, st_full, ns_full = _gpu_grads(torch, wl, np.arange(n))
+    keep = np.arange(0, n, 3)
+    other = np.setdiff1d(np.arange(n), keep)
+    mixed = np.arange(n)
+    mixed[other] = np.random.default_rng(5).permutation(other)
+    got, _, st_mix, ns_mix = _gpu_grads(torch, wl, mixed)
+    assert np.array_equal(st_full[keep], st_mix[keep])
+    assert np.array_equal(ns_full[keep], ns_mix[keep])
+    segs = (ns_full - 1) // 16
+    print(name, "segments per lane:", segs.min(), segs.max())
+    assert np.any(got[:, keep] != 0.0)
+    assert np.array_equal(full[:, keep], got[:, keep])
+    head, _, _, _ = _gpu_grads(torch, wl, np.arange(77))
+    assert np.array_equal(full[:, :77], head)
