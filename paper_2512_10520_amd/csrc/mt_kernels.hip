@@ -1433,7 +1433,14 @@ __device__ __forceinline__ void block_partial(F &&term, int64_t begin, int64_t e
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    for (int64_t i = begin + threadIdx.x; i < end; i += kRedBlock) term(i, acc);
+    // eight elements per thread in flight; each accumulator still adds its
+    // elements in index order
+    int64_t i = begin + threadIdx.x;
+    for (; i + 7 * kRedBlock < end; i += 8 * kRedBlock) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) term(i + u * kRedBlock, acc);
+    }
+    for (; i < end; i += kRedBlock) term(i, acc);
 #pragma unroll
     for (int c = 0; c < NC; ++c) red[c][threadIdx.x] = acc[c];
     __syncthreads();
@@ -1500,8 +1507,17 @@ __global__ void k_pass2(const double *partial, int nb, int n_cols, int n_variant
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_variants * n_cols) return;
     const int v = i / n_cols, c = i - v * n_cols;
+    const double *p = partial + (size_t)v * nb * n_cols + c;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[((size_t)v * nb + b) * n_cols + c];
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {        // loads of eight partials in flight, sums in order of b
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = p[(size_t)(b + u) * n_cols];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; b < nb; ++b) s += p[(size_t)b * n_cols];
     out[i] = s;
 }
 
