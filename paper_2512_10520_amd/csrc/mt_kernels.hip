@@ -1479,27 +1479,19 @@ __global__ void __launch_bounds__(kRedBlock) k_tally_pass1(DevIO io, int64_t n, 
     block_partial<3>(term, begin, end, partial + ((size_t)v * nb + b) * 3);
 }
 
+// One block per (chunk b, variant v, column c): each column is summed on
+// its own, in the same order and tree as every other column.
 __global__ void __launch_bounds__(kRedBlock) k_colsum_pass1(const double *vals, int n_cols,
                                                             int64_t n, int64_t lanes,
                                                             double *partial) {
-    const int v = blockIdx.y, b = blockIdx.x, nb = gridDim.x;
+    const int v = blockIdx.y, b = blockIdx.x, nb = gridDim.x, c = blockIdx.z;
     const int64_t chunk = (n + nb - 1) / nb;
     const int64_t base = (int64_t)v * n;
     const int64_t begin = base + min((int64_t)b * chunk, n);
     const int64_t end = base + min((int64_t)(b + 1) * chunk, n);
-    for (int c0 = 0; c0 < n_cols; c0 += 4) {
-        const double *col = vals + (size_t)c0 * lanes;
-        const int nc = min(4, n_cols - c0);
-        auto term = [&](int64_t i, double *acc) {
-            for (int c = 0; c < nc; ++c) acc[c] += col[(size_t)c * lanes + i];
-        };
-        double tmp[4];
-        block_partial<4>(term, begin, end, tmp);
-        if (threadIdx.x == 0)
-            for (int c = 0; c < nc; ++c)
-                partial[((size_t)v * nb + b) * n_cols + c0 + c] = tmp[c];
-        __syncthreads();
-    }
+    const double *col = vals + (size_t)c * lanes;
+    auto term = [&](int64_t i, double *acc) { acc[0] += col[i]; };
+    block_partial<1>(term, begin, end, partial + ((size_t)v * nb + b) * n_cols + c);
 }
 
 // out[v][c] = sum over b of partial[v][b][c], in order of b.
@@ -1692,8 +1684,8 @@ hipError_t launch_tally(const DevIO &io, int64_t n, int32_t n_variants, double z
 hipError_t launch_column_sums(const double *vals, int32_t n_cols, int64_t n, int32_t n_variants,
                               double *partial, int32_t n_part_blocks, double *out, hipStream_t s) {
     if (n_cols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_colsum_pass1, dim3(n_part_blocks, n_variants), dim3(kRedBlock), 0, s,
-                       vals, n_cols, n, n * n_variants, partial);
+    hipLaunchKernelGGL(k_colsum_pass1, dim3(n_part_blocks, n_variants, n_cols), dim3(kRedBlock),
+                       0, s, vals, n_cols, n, n * n_variants, partial);
     const int nout = n_variants * n_cols;
     hipLaunchKernelGGL(k_pass2, dim3((nout + 127) / 128), dim3(128), 0, s, partial, n_part_blocks,
                        n_cols, n_variants, out);
