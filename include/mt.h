@@ -184,7 +184,8 @@ int mt_load_blocks(int32_t n, const double *block, const int32_t *material, cons
  * the per-box field and interpolated trilinearly.  Node (i, j, k) sits at
  * lo + (i, j, k) * (hi - lo) / (n - 1); outside [lo, hi] the map gives zero.
  *
- *   b   host float [nz][ny][nx][3] tesla; NULL unloads the map.
+ *   b   host float [nz][ny][nx][3] tesla, every value finite; NULL unloads
+ *       the map.
  * Requires nx, ny, nz >= 2 and lo < hi on every axis.  The device holds a
  * cell-major copy, the 8 corner values of each cell in one 128-byte record
  * (128 (nx-1)(ny-1)(nz-1) bytes), so that a trilinear lookup reads one cache
@@ -266,6 +267,10 @@ typedef struct mt_params {
  * With use_graph, the first call for a given argument set captures
  * queue reset + transport (+ tallies) into a hipGraph that later identical
  * calls replay; changing any pointer or parameter captures a new graph.
+ * Library-owned workspaces (the persistent form's work counter, the tally
+ * and scale-gradient partial sums, the adjoint's segment history) are shared
+ * by every call: calls whose device work may overlap (on different streams)
+ * race on them, so issue such calls on one stream or wait between them.
  * Errors: MT_ERR_NOT_LOADED, MT_ERR_INVALID_ARG, MT_ERR_SHAPE, MT_ERR_HIP.
  */
 int mt_propagate(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
@@ -302,6 +307,28 @@ int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in
 int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
                 mt_result *res, void *hip_stream, int32_t *best_block,
                 int32_t *best_compact, float *best_ms);
+
+/*
+ * Tuning switches of the library; none of them changes a result bit (each is
+ * compared bit for bit with the default by a GPU test).  Settings are global,
+ * kept until mt_release() and default as listed.
+ *
+ *   MT_OPT_GUIDE_BITS           resolution (bits of the cell word) of the
+ *                               inverse-CDF guide table: 0 = automatic (one
+ *                               entry per two cells, at most 2^16; default) or
+ *                               1..16.  Applies from the next histogram load.
+ *   MT_OPT_ADJOINT_BLOCK        threads per block of the adjoint kernel: 64
+ *                               (default), 128, 192 or 256.
+ *   MT_OPT_ADJOINT_LDS_HISTORY  1: the adjoint keeps a segment's pre-kick
+ *                               momenta in LDS instead of device memory
+ *                               (geometries without a field map; ignored with
+ *                               one); 0 (default).
+ * Errors: MT_ERR_INVALID_ARG (unknown option or value out of range).
+ */
+#define MT_OPT_GUIDE_BITS           1
+#define MT_OPT_ADJOINT_BLOCK        2
+#define MT_OPT_ADJOINT_LDS_HISTORY  3
+int mt_set_option(int32_t option, int64_t value);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *mt_last_error(void);

@@ -9,9 +9,7 @@ import os
 import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# MT_LIBRARY points at another build of the same library (e.g. to compare two
-# builds on one machine); by default the in-tree build is used.
-LIB_PATH = os.environ.get("MT_LIBRARY") or os.path.join(_HERE, "libmt.so")
+LIB_PATH = os.path.join(_HERE, "libmt.so")
 
 MT_OK = 0
 ERRORS = {-1: "MT_ERR_INVALID_ARG", -2: "MT_ERR_SHAPE", -3: "MT_ERR_EMPTY_HIST",
@@ -20,14 +18,15 @@ MT_MODE_PLAIN, MT_MODE_PERSISTENT, MT_MODE_VARIANT_WAVES = 0, 1, 2
 MT_SAMPLER_CDF, MT_SAMPLER_ALIAS = 0, 1
 MT_INTERP_TRILINEAR, MT_INTERP_NEAREST = 0, 1
 MT_AXIS_LOG_LOSS, MT_AXIS_LOG_SCAT = 1, 2
+MT_OPT_GUIDE_BITS, MT_OPT_ADJOINT_BLOCK, MT_OPT_ADJOINT_LDS_HISTORY = 1, 2, 3
 ST_RUNNING, ST_PMIN, ST_ZMAX, ST_XMAX, ST_YMAX, ST_MAXSTEPS, ST_INVALID = range(7)
 CKPT_EVERY = 16
 
 # Names of every entry point the header declares (checked by the CPU tests).
 EXPORTS = ("mt_load_histograms", "mt_load_histograms_ex", "mt_optimal_edges",
            "mt_load_geometry", "mt_load_blocks", "mt_load_field", "mt_propagate",
-           "mt_propagate_backward", "mt_autotune", "mt_last_error", "mt_release",
-           "mt_device_info")
+           "mt_propagate_backward", "mt_autotune", "mt_set_option", "mt_last_error",
+           "mt_release", "mt_device_info")
 
 
 class MtParams(C.Structure):
@@ -80,6 +79,7 @@ def load():
             L.mt_autotune.argtypes = [C.POINTER(MtParams), i64, C.POINTER(MtMuons),
                                       C.POINTER(MtMuons), C.POINTER(MtResult), vp,
                                       C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_float)]
+            L.mt_set_option.argtypes = [i32, i64]
             L.mt_last_error.restype = C.c_char_p
             L.mt_last_error.argtypes = []
             L.mt_release.restype = None

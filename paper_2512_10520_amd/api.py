@@ -106,6 +106,16 @@ def load_workload(wl) -> None:
     load_field(wl.field)
 
 
+OPTIONS = {"guide_bits": _lib.MT_OPT_GUIDE_BITS, "adjoint_block": _lib.MT_OPT_ADJOINT_BLOCK,
+           "adjoint_lds_history": _lib.MT_OPT_ADJOINT_LDS_HISTORY}
+OPTION_DEFAULTS = {"guide_bits": 0, "adjoint_block": 64, "adjoint_lds_history": 0}
+
+
+def set_option(name: str, value: int) -> None:
+    """Set a tuning switch (``mt_set_option``); none changes a result."""
+    check(_lib.load().mt_set_option(OPTIONS[name], int(value)))
+
+
 def last_error() -> str:
     return _lib.load().mt_last_error().decode(errors="replace")
 

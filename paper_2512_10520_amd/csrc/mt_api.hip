@@ -96,6 +96,10 @@ struct State {
     std::vector<GraphEntry> graphs;
     std::vector<TuneEntry> tuned;
     int cu_count = 0;
+    // tuning switches (mt_set_option); none changes a result bit
+    int opt_guide_bits = 0;          // 0: automatic
+    int opt_adjoint_block = 64;
+    int opt_adjoint_lds_history = 0;
 };
 
 State g;
@@ -118,6 +122,24 @@ void drop_graphs() {
         if (e.graph) (void)hipGraphDestroy(e.graph);
     }
     g.graphs.clear();
+}
+
+// Captured graphs hold the addresses of the workspace buffers (the
+// persistent queue, the zeroing dummy and the tally partials) baked into
+// their kernel nodes, and their cache key does not: a graph whose workspace
+// has been reallocated since its capture must never be replayed.  Growing a
+// buffer frees the old one (hipFree waits for the device), then every cached
+// graph is dropped.
+struct WorkspaceAddr {
+    void *queue, *partial, *zero;
+};
+
+WorkspaceAddr workspace_addr() { return {g.queue.p, g.partial.p, g.zero_dummy.p}; }
+
+void drop_graphs_if_moved(const WorkspaceAddr &before) {
+    if (before.queue != g.queue.p || before.partial != g.partial.p ||
+        before.zero != g.zero_dummy.p)
+        drop_graphs();
 }
 
 void tables_changed() {
@@ -351,9 +373,12 @@ int propagate_impl(const mt_params *p, int64_t n, const mt_muons *in, mt_muons *
     int rc = validate(p, n, in, out, res, false, c);
     if (rc) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const WorkspaceAddr ws = workspace_addr();
     if (c.lanes == 0) {
         if (p->tally) {
-            if ((rc = g.queue.ensure(sizeof(unsigned long long)))) return rc;
+            rc = g.queue.ensure(sizeof(unsigned long long));
+            drop_graphs_if_moved(ws);
+            if (rc) return rc;
             MT_HIP(mt::launch_queue_reset(reinterpret_cast<unsigned long long *>(g.queue.p),
                                           p->tally, (int64_t)p->n_variants * 3, s));
         }
@@ -368,6 +393,7 @@ int propagate_impl(const mt_params *p, int64_t n, const mt_muons *in, mt_muons *
     if (force_block) c.block = force_block;
     if (force_compact) c.compact = force_compact;
     rc = prepare_workspace(p, c);
+    drop_graphs_if_moved(ws);
     if (rc) return rc;
     if (allow_graph && p->use_graph && p->mode != MT_MODE_PLAIN) {
         struct K {
@@ -532,10 +558,7 @@ int mt_load_histograms_ex(int32_t n_mat, int32_t n_pbin, const double *p_edges, 
     int gbits = 1;
     while (gbits < 16 && ((int64_t)1 << gbits) < K) ++gbits;
     if (gbits > 1) --gbits;
-    if (const char *env = std::getenv("MT_GUIDE_BITS")) {
-        int v = std::atoi(env);
-        if (v >= 1 && v <= 16) gbits = v;
-    }
+    if (g.opt_guide_bits > 0) gbits = g.opt_guide_bits;
     const int64_t G = (int64_t)1 << gbits;
     std::vector<uint32_t> cdf((size_t)(nh * K)), totals((size_t)nh);
     std::vector<uint2> guide((size_t)(nh * G));
@@ -589,7 +612,7 @@ int mt_load_histograms_ex(int32_t n_mat, int32_t n_pbin, const double *p_edges, 
     H.n_scat = n_scat;
     H.n_cells = (int32_t)K;
     H.gbits = gbits;
-    H.nscat_magic = (uint32_t)((0x100000000ull / (uint64_t)n_scat) + 1);
+    H.nscat_magic = 0xFFFFFFFFu / (uint32_t)n_scat;
     // axis origin and bin width in the axis' own units (log10 on a log axis)
     const double l0 = log_l ? std::log10(loss_lo) : loss_lo, l1 = log_l ? std::log10(loss_hi) : loss_hi;
     const double s0 = log_s ? std::log10(scat_lo) : scat_lo, s1 = log_s ? std::log10(scat_hi) : scat_hi;
@@ -884,6 +907,10 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
     if ((size_t)nx * ny * nz > 0x7FFFFFFFull)
         return fail(MT_ERR_LIMIT, "the field map has %zu nodes, more than 2^31 - 1",
                     (size_t)nx * ny * nz);
+    for (size_t i = 0; i < 3 * (size_t)nx * ny * nz; ++i)
+        if (!std::isfinite(b[i]))
+            return fail(MT_ERR_INVALID_ARG, "field map value %zu (node %zu, component %zu) is "
+                                            "not finite", i, i / 3, i % 3);
     std::vector<float4> m;
     try {
         m.resize(cells * 8);
@@ -946,9 +973,11 @@ int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in
         return fail(MT_ERR_INVALID_ARG, "g_out and g_in must be non-NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const int n_mag = g.T.geom.n_mag;
+    const WorkspaceAddr ws = workspace_addr();
     if (c.lanes == 0) {
         if (g_scales && n_mag > 0) {
             rc = g.queue.ensure(8);
+            drop_graphs_if_moved(ws);
             if (rc) return rc;
             MT_HIP(mt::launch_queue_reset(reinterpret_cast<unsigned long long *>(g.queue.p),
                                           g_scales, (int64_t)params->n_variants * n_mag, s));
@@ -957,14 +986,14 @@ int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in
     }
     if ((rc = g.scratch.ensure((size_t)mt::adjoint_scratch_bytes(g.T, c.lanes)))) return rc;
     if ((rc = g.gs_lane.ensure((size_t)std::max(1, n_mag) * c.lanes * sizeof(double)))) return rc;
-    const int block = std::getenv("MT_ADJOINT_BLOCK") ? std::atoi(std::getenv("MT_ADJOINT_BLOCK")) : 64;
-    if (block < 64 || block > 256 || block % 64)
-        return fail(MT_ERR_INVALID_ARG, "MT_ADJOINT_BLOCK must be 64, 128, 192 or 256");
     MT_HIP(mt::launch_adjoint(g.T, c.R, c.io, g_out, g_in,
-                              reinterpret_cast<double *>(g.gs_lane.p), g.scratch.p, block, s));
+                              reinterpret_cast<double *>(g.gs_lane.p), g.scratch.p,
+                              g.opt_adjoint_block, g.opt_adjoint_lds_history != 0, s));
     if (g_scales && n_mag > 0) {
         const int nb = n_part_blocks(c.n);
-        if ((rc = g.partial.ensure((size_t)nb * c.n_variants * n_mag * sizeof(double)))) return rc;
+        rc = g.partial.ensure((size_t)nb * c.n_variants * n_mag * sizeof(double));
+        drop_graphs_if_moved(ws);
+        if (rc) return rc;
         MT_HIP(mt::launch_column_sums(reinterpret_cast<const double *>(g.gs_lane.p), n_mag, c.n,
                                       c.n_variants, reinterpret_cast<double *>(g.partial.p), nb,
                                       g_scales, s));
@@ -1037,6 +1066,29 @@ int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons
     return MT_OK;
 }
 
+int mt_set_option(int32_t option, int64_t value) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    switch (option) {
+    case MT_OPT_GUIDE_BITS:
+        if (value < 0 || value > 16)
+            return fail(MT_ERR_INVALID_ARG, "MT_OPT_GUIDE_BITS must be 0 (automatic) or 1..16");
+        g.opt_guide_bits = (int)value;
+        return MT_OK;
+    case MT_OPT_ADJOINT_BLOCK:
+        if (value < 64 || value > 256 || value % 64)
+            return fail(MT_ERR_INVALID_ARG, "MT_OPT_ADJOINT_BLOCK must be 64, 128, 192 or 256");
+        g.opt_adjoint_block = (int)value;
+        return MT_OK;
+    case MT_OPT_ADJOINT_LDS_HISTORY:
+        if (value != 0 && value != 1)
+            return fail(MT_ERR_INVALID_ARG, "MT_OPT_ADJOINT_LDS_HISTORY must be 0 or 1");
+        g.opt_adjoint_lds_history = (int)value;
+        return MT_OK;
+    default:
+        return fail(MT_ERR_INVALID_ARG, "unknown option %d", option);
+    }
+}
+
 const char *mt_last_error(void) { return g_err.c_str(); }
 
 void mt_release(void) {
@@ -1055,6 +1107,9 @@ void mt_release(void) {
     g.n_mat = g.n_pbin = 0;
     g.max_material = -1;
     g.tuned.clear();
+    g.opt_guide_bits = 0;
+    g.opt_adjoint_block = 64;
+    g.opt_adjoint_lds_history = 0;
     ++g.version;
 }
 

@@ -28,7 +28,8 @@ struct DevHist {
     const double *edges2;        // [n_pbin + 1] squared momentum edges
     const uint2 *alias;          // [h][c] alias method: (24-bit threshold split, alias cell)
     int32_t n_mat, n_pbin, n_loss, n_scat, n_cells, gbits;
-    uint32_t nscat_magic;        // floor(2^32 / n_scat) + 1 for exact c / n_scat, c < 2^16
+    uint32_t nscat_magic;        // floor((2^32 - 1) / n_scat): c / n_scat = umulhi(c + 1, it),
+                                 // exact for n_scat >= 1 and c < 2^16
     float loss_lo, loss_w, scat_lo, scat_w;   // log10 units on a logarithmic axis
     int32_t log_loss, log_scat;  // axis binned uniformly in log10 of the value
 };
@@ -117,7 +118,7 @@ hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n
                               hipStream_t s);
 hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
                           const double *g_out, double *g_in, double *gs_lane, void *scratch,
-                          int block, hipStream_t s);
+                          int block, bool lds_history, hipStream_t s);
 // Deterministic per-variant sums.  tally: (zmax count, hit count, sigmoid sum);
 // column sums: out[v][c] = sum over lanes of variant v of vals[c][lane].
 hipError_t launch_tally(const DevIO &io, int64_t n, int32_t n_variants, double z_det,

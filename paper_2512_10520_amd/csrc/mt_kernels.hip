@@ -739,7 +739,9 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         const int h = (int)__umul24((uint32_t)mat, (uint32_t)T.hist.n_pbin) + ibin;
         if constexpr ((F & kAlias) != 0) cell = alias_cell(T.hist, h, w);
         else cell = sample_cell(T.hist, S, h, w.x);
-        const int il = (int)__umulhi((uint32_t)cell, T.hist.nscat_magic);
+        // cell / n_scat as umulhi(cell + 1, floor((2^32 - 1) / n_scat)): exact
+        // for every n_scat >= 1 and cell < 2^16
+        const int il = (int)__umulhi((uint32_t)cell + 1u, T.hist.nscat_magic);
         const int is = cell - il * T.hist.n_scat;
         const float v1 = (float)(w.y >> 8) * 0x1p-24f;
         const float v2 = (float)(w.z >> 8) * 0x1p-24f;
@@ -988,8 +990,8 @@ k_persistent(Tables T, DevRun R, DevIO io, int compact,
 // G steps lane l forms the block of step k + (l mod G) for its group's muon
 // into the wavefront's 1 KB of LDS, and at step k every lane reads its
 // group's entry k mod G (one address per group, which the LDS broadcasts;
-// the wavefront's own LDS writes and reads are ordered, so no barrier is
-// needed).  The lanes of a wavefront step in lockstep (all start at step 0,
+// the wavefront's own LDS writes and reads are executed in order, so only
+// the compiler's ordering needs a wave barrier).  The lanes of a wavefront step in lockstep (all start at step 0,
 // and each pass of the loop is one step for every lane still running), which
 // is what makes the shared block the right one; a lane whose muon has
 // stopped still forms its block for the others.  Wavefront w takes the
@@ -1031,7 +1033,15 @@ __global__ void __launch_bounds__(1024) k_variant_waves(Tables T, DevRun R, DevI
     const int base = lane & ~gm;
     for (int k = 0; __ballot(running) != 0; ++k) {
         const int sl = k & gm;
-        if (sl == 0) wblk[lane] = philox_step(P, (uint32_t)(k + (lane & gm)), R.key0, R.key1);
+        if (sl == 0) {
+            // the wavefront's LDS accesses are executed in order; the wave
+            // barriers keep the compiler from moving the reads of the last
+            // group of steps below this write or the reads of the next group
+            // above it
+            __builtin_amdgcn_wave_barrier();
+            wblk[lane] = philox_step(P, (uint32_t)(k + (lane & gm)), R.key0, R.key1);
+            __builtin_amdgcn_wave_barrier();
+        }
         if (running) {
             const uint4 w = wblk[base + sl];      // one address per group: a broadcast
             running = advance<F | kShared>(L, T, S, R, sc, w);
@@ -1638,26 +1648,20 @@ hipError_t launch_queue_reset(unsigned long long *queue, double *zero, int64_t n
     return hipGetLastError();
 }
 
-// Where the adjoint keeps a segment's start states: device memory (default;
-// at 16 steps x 12 B per lane it stays L2/Infinity-Cache resident and leaves
-// LDS free for occupancy) or LDS (MT_ADJOINT_HISTORY=lds, no field map).
-static bool adjoint_lds_history(const Tables &T) {
-    if (T.field.map != nullptr) return false;
-    const char *env = getenv("MT_ADJOINT_HISTORY");
-    return env && env[0] == 'l';
-}
-
 int64_t adjoint_scratch_bytes(const Tables &T, int64_t lanes) {
     return (int64_t)kCkptEvery * (sizeof(Float3r) + 3 * sizeof(double)) * lanes;
 }
 
+// Where the adjoint keeps a segment's start states: device memory (default;
+// at 16 steps x 12 B per lane it stays L2/Infinity-Cache resident and leaves
+// LDS free for occupancy) or, on request and without a field map, LDS.
 hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
                           const double *g_out, double *g_in, double *gs_lane, void *scratch,
-                          int block, hipStream_t s) {
+                          int block, bool lds_history, hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
     const int64_t grid = (R.lanes + block - 1) / block;
     const bool map = T.field.map != nullptr;
-    const bool ldsh = adjoint_lds_history(T);
+    const bool ldsh = lds_history && !map;
     size_t shm = (size_t)((T.lds.bytes + 15) & ~15) + (size_t)T.geom.n_mag * block * sizeof(double);
     if (ldsh) shm += (size_t)kCkptEvery * 3 * block * sizeof(float);   // p0 per step
     char *sc = reinterpret_cast<char *>(scratch);

@@ -143,6 +143,37 @@ def test_geometry_and_field_validation(L):
     b = np.zeros((2, 2, 1, 3), np.float32)
     assert L.mt_load_field(1, 2, 2, lo.ctypes.data, hi.ctypes.data, b.ctypes.data) == -1
     assert L.mt_load_field(2, 2, 2, hi.ctypes.data, lo.ctypes.data, b.ctypes.data) == -1
+    for bad in (np.nan, np.inf, -np.inf):
+        b = np.zeros((2, 2, 2, 3), np.float32)
+        b[1, 0, 1, 2] = bad
+        assert L.mt_load_field(2, 2, 2, lo.ctypes.data, hi.ctypes.data, b.ctypes.data) == -1
+        assert "not finite" in _err(L) and "node 5, component 2" in _err(L)
+
+
+def test_option_validation(L):
+    for opt, bad in ((_lib.MT_OPT_GUIDE_BITS, -1), (_lib.MT_OPT_GUIDE_BITS, 17),
+                     (_lib.MT_OPT_ADJOINT_BLOCK, 96), (_lib.MT_OPT_ADJOINT_BLOCK, 512),
+                     (_lib.MT_OPT_ADJOINT_LDS_HISTORY, 2), (99, 0)):
+        assert L.mt_set_option(opt, bad) == -1, (opt, bad)
+    for opt, good in ((_lib.MT_OPT_GUIDE_BITS, 0), (_lib.MT_OPT_ADJOINT_BLOCK, 64),
+                      (_lib.MT_OPT_ADJOINT_LDS_HISTORY, 0)):
+        assert L.mt_set_option(opt, good) == 0
+
+
+def test_cell_split_division_is_exact():
+    """The kernels split a cell index c into (c / n_scat, c mod n_scat) with
+    one high-half product: c / n_scat = floor((c + 1) m / 2^32) with
+    m = floor((2^32 - 1) / n_scat), exact for every n_scat >= 1 and c < 2^16
+    (the largest histogram has 2^16 cells).  Checked for all n_scat up to 1024,
+    every power of two and the largest values, over every c of the largest
+    histogram with that n_scat."""
+    sizes = list(range(1, 1025)) + [2 ** k for k in range(11, 17)] + [65535, 40000, 32769]
+    for s in sizes:
+        m = np.uint64((2 ** 32 - 1) // s)
+        K = max(1, 65536 // s) * s
+        c = np.arange(K, dtype=np.uint64)
+        il = ((c + np.uint64(1)) * m) >> np.uint64(32)
+        assert np.array_equal(il, c // np.uint64(s)), s
 
 
 def test_block_geometry_validation(L):

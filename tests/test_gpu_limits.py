@@ -1,8 +1,9 @@
 """GPU parity at the documented table limits: the largest histogram
 (n_loss * n_scat = 65536 cells, the guide packs 16-bit cell indices; one
-pattern has more wide guide buckets than the second-level guide refines)
-with both samplers, 1024 momentum bins, and 64 overlapping boxes / 64 convex
-blocks (one 64-bit candidate mask) probed at random and on-face points."""
+pattern puts three or more cells into many guide buckets, so the probe loop
+runs often) with both samplers, 1024 momentum bins, and 64 overlapping boxes
+/ 64 convex blocks (one 64-bit candidate mask) probed at random and on-face
+points."""
 import dataclasses
 
 import numpy as np
@@ -35,8 +36,8 @@ def test_largest_histogram_and_most_bins(sampler):
         c = rng.integers(0, 3, size=(nl, ns)).astype(np.uint32) * (rng.random((nl, ns)) < 0.2)
         c[rng.integers(nl, size=5), rng.integers(ns, size=5)] += rng.integers(1000, 100000, 5).astype(np.uint32)
         counts[0, i] = c
-    # pattern 3: small counts everywhere, so that more guide buckets span three
-    # or more cells than the second-level guide refines (the unrefined path)
+    # pattern 3: small counts everywhere, so that many guide buckets span three
+    # or more cells and the draw falls through to the probe loop
     counts[0, 3] = rng.integers(0, 4, size=(nl, ns)).astype(np.uint32)
     # 1024 momentum bins reuse the 4 patterns (bin i -> pattern i % 4)
     full = np.ascontiguousarray(counts[:, np.arange(n_pbin) % 4])

@@ -135,6 +135,32 @@ def test_invalid_and_degenerate_inputs():
     assert g0["status"][0] == oracle.ST_STEPS and g0["n_steps"][0] == 0
 
 
+@pytest.mark.parametrize("n_loss,n_scat", [(16, 1), (1, 16), (1, 1)])
+def test_single_row_and_single_column_histograms(n_loss, n_scat):
+    """Histograms with one kick bin (the cell index is the loss index), one
+    loss bin (the cell index is the kick index) or a single cell: cells,
+    bins and volumes step by step against the oracle."""
+    rng = np.random.default_rng(n_loss * 100 + n_scat)
+    counts = rng.integers(1, 40, size=(n_loss, n_scat)).astype(np.uint32)
+    hist = CU.flat_histograms(n_pbin=6, n_loss=n_loss, n_scat=n_scat, counts=counts)
+    geom = CU.geometry([[-1, 1, -1, 1, 0, 3]], [0], b_box=[[0.0, 1.0, 0.0]],
+                       world=(1.0, 1.0, 3.0))
+    n = 2000
+    mu = CU.muons(rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n), -0.0075,
+                  rng.normal(0, 0.1, n), rng.normal(0, 0.1, n), rng.uniform(5, 200, n),
+                  np.where(np.arange(n) % 2, 1, -1))
+    wl = CU.workload(hist, geom, mu, max_steps=400, p_min=0.5)
+    g = gpu_run(wl, trace_steps=200, n_trace=n)
+    o = oracle_run(wl, np.arange(n), trace_steps=200)
+    s = compare(g, o, trace_rows=n, label=f"hist {n_loss}x{n_scat}")
+    print("hist", n_loss, n_scat, s)
+    cells = g["trace"][:, :, 2]
+    drawn = cells[cells >= 0]
+    assert drawn.size > 10_000 and drawn.max() < n_loss * n_scat
+    if n_loss * n_scat > 1:
+        assert len(np.unique(drawn)) == n_loss * n_scat
+
+
 def test_empty_launch():
     wl = W.make_workload("tiny", n_muons=0)
     g = gpu_run(wl)

@@ -52,3 +52,39 @@ def test_release_and_reload_between_geometry_kinds():
     for k in ra:
         assert np.array_equal(ra[k], ra2[k]), k
         assert np.array_equal(rb[k], rb2[k]), k
+
+
+def test_graph_replay_after_workspace_grows():
+    """A graph captured with a small tally holds the address of the library's
+    tally partials.  A later call needing a larger partial buffer (a tally
+    over more muons, then a backward pass with scale gradients) reallocates
+    it, which drops the cached graphs; replaying the first call then
+    captures again and gives the eager tally."""
+    import torch
+    from paper_2512_10520_amd import api
+    t = {"z_det": 30.0, "r_ap": 1.0, "r_scale": 0.01}
+    wl = W.make_workload("scan", n_muons=200_000, n_variants=3, n_fill=200_000)
+    api.load_workload(wl)
+    sc = torch.from_numpy(np.ascontiguousarray(wl.run.scales, np.float32)).cuda()
+    small = api.DeviceMuons.from_host(wl.muons.take(np.arange(1000)))
+    big = api.DeviceMuons.from_host(wl.muons)
+    spec_g = api.RunSpec.from_workload(wl, mode="persistent", use_graph=True)
+    spec_e = api.RunSpec.from_workload(wl, mode="persistent")
+    eager = api.propagate(small, spec_e, scales=sc, tally=t)
+    torch.cuda.synchronize()
+    ref = eager.tally.cpu().numpy()
+    out = api.alloc_result(spec_g, len(small), "cuda", tally=True)
+    api.propagate(small, spec_g, scales=sc, tally=t, out=out)          # capture
+    torch.cuda.synchronize()
+    assert np.array_equal(out.tally.cpu().numpy(), ref)
+    api.propagate(big, spec_e, scales=sc, tally=t)                      # partials grow
+    spec_d = api.RunSpec.from_workload(wl)
+    fwd = api.propagate(big, spec_d, scales=sc, ckpt=True)
+    g_out = torch.ones((6, 3 * len(big)), dtype=torch.float64, device="cuda")
+    api.propagate_backward(big, spec_d, fwd, g_out, scales=sc, n_mag=8)  # and again
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.tally.fill_(-1.0)
+        api.propagate(small, spec_g, scales=sc, tally=t, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.tally.cpu().numpy(), ref), rep

@@ -1,11 +1,10 @@
 """GPU: the library's tuning switches change speed, never results.
 
-MT_GUIDE_BITS sets the inverse-CDF guide resolution at table load (a coarser
-guide leaves wider brackets to the probe), MT_ADJOINT_HISTORY=lds keeps the
-adjoint's segment history in LDS instead of device memory, MT_ADJOINT_BLOCK
-sets the adjoint's block size.  Each must give the default's bits."""
-import os
-
+mt_set_option sets the inverse-CDF guide resolution at table load
+(MT_OPT_GUIDE_BITS: a coarser guide leaves wider brackets to the probe), keeps
+the adjoint's segment history in LDS instead of device memory
+(MT_OPT_ADJOINT_LDS_HISTORY) and sets the adjoint's block size
+(MT_OPT_ADJOINT_BLOCK).  Each must give the default's bits."""
 import numpy as np
 import pytest
 
@@ -26,20 +25,21 @@ def _cuda():
     _lib.load()
 
 
-class _env:
+class _option:
+    """Set tuning switches for the duration of a block, then restore the defaults."""
+
     def __init__(self, **kw):
         self.kw = kw
 
     def __enter__(self):
-        self.old = {k: os.environ.get(k) for k in self.kw}
-        os.environ.update({k: str(v) for k, v in self.kw.items()})
+        from paper_2512_10520_amd import api
+        for k, v in self.kw.items():
+            api.set_option(k, v)
 
     def __exit__(self, *a):
-        for k, v in self.old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+        from paper_2512_10520_amd import api
+        for k in self.kw:
+            api.set_option(k, api.OPTION_DEFAULTS[k])
 
 
 @pytest.mark.parametrize("bits", [4, 9, 16])
@@ -49,7 +49,7 @@ def test_guide_resolution_does_not_change_draws(bits):
     resolution; 4 bits leaves brackets of hundreds of cells to the probe)."""
     wl = W.make_workload("block", n_muons=20_000, n_fill=200_000)
     ref = gpu_run(wl, trace_steps=260, n_trace=300)
-    with _env(MT_GUIDE_BITS=bits):
+    with _option(guide_bits=bits):
         got = gpu_run(wl, trace_steps=260, n_trace=300)     # tables reloaded under the switch
     for k in KEYS + ("trace",):
         assert np.array_equal(ref[k], got[k]), (bits, k)
@@ -67,13 +67,13 @@ def _grads(torch, wl, n):
     return x0.grad.cpu().numpy(), sc.grad.cpu().numpy()
 
 
-@pytest.mark.parametrize("env", [{"MT_ADJOINT_HISTORY": "lds"}, {"MT_ADJOINT_BLOCK": 128},
-                                 {"MT_ADJOINT_BLOCK": 256}])
+@pytest.mark.parametrize("env", [{"adjoint_lds_history": 1}, {"adjoint_block": 128},
+                                 {"adjoint_block": 256}])
 def test_adjoint_switches_give_the_same_gradients(env):
     import torch
     wl = W.make_workload("diff", n_muons=3000, n_fill=200_000)
     gx, gs = _grads(torch, wl, 3000)
-    with _env(**env):
+    with _option(**env):
         hx, hs = _grads(torch, wl, 3000)
     assert np.array_equal(gx, hx), env
     assert np.array_equal(gs, hs), env
