@@ -106,6 +106,14 @@ def lib():
             L.oracle_pbin.restype = C.c_int32
             L.oracle_trilinear.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p]
             L.oracle_nearest.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p]
+            for name in ("oracle_geom_margin", "oracle_map_margin"):
+                getattr(L, name).argtypes = [C.POINTER(_Problem), C.c_void_p]
+                getattr(L, name).restype = C.c_double
+            L.oracle_break_margin.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_double,
+                                              C.POINTER(C.c_double)]
+            L.oracle_break_margin.restype = C.c_double
+            L.oracle_bin_margin.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_double]
+            L.oracle_bin_margin.restype = C.c_double
             L.oracle_propagate.argtypes = [C.POINTER(_Problem), C.c_int64, C.POINTER(_In),
                                            C.POINTER(_Out), C.c_int32]
             L.oracle_propagate.restype = C.c_int
@@ -184,14 +192,16 @@ class Result:
 
 
 def propagate(wl, idx=None, variant=None, muons=None, scales=None, seed=None,
-              trace_steps: int = 0, kick_steps: int = 0, n_threads: int = 0) -> Result:
+              trace_steps: int = 0, kick_steps: int = 0, n_threads: int = 0,
+              margins: bool = True) -> Result:
     """Run the oracle on muons ``idx`` of the workload (default: all).
 
     ``idx`` doubles as the Philox muon index of each muon.  ``variant`` gives
     each muon's field-scale variant (default 0).  ``muons`` optionally replaces
     the initial states (a [6][n] float64 array plus charges from the workload)
     while keeping the Philox indices, which is how finite differences on
-    common random numbers are formed.
+    common random numbers are formed.  ``margins=False`` skips the decision
+    margins (margin_pos / margin_p come back as infinity, step_margin None).
     """
     L = lib()
     m = wl.muons
@@ -216,10 +226,14 @@ def propagate(wl, idx=None, variant=None, muons=None, scales=None, seed=None,
     mp = np.zeros(n, np.float64)
     trace = np.full((n, trace_steps, 3), -2, np.int32) if trace_steps > 0 else None
     kicks = np.zeros((n, kick_steps, 3), np.float32) if kick_steps > 0 else None
-    smarg = np.full((n, trace_steps + 1, 2), np.inf) if trace_steps > 0 else None
+    smarg = np.full((n, trace_steps + 1, 2), np.inf) if trace_steps > 0 and margins else None
+    if not margins:
+        mpos[:] = np.inf
+        mp[:] = np.inf
     I = _In(*[st[a].ctypes.data for a in range(6)], q.ctypes.data, idx.ctypes.data, _ptr(var))
     O = _Out(*[out_state[a].ctypes.data for a in range(6)], status.ctypes.data, nst.ctypes.data,
-             vol.ctypes.data, mpos.ctypes.data, mp.ctypes.data, _ptr(trace), trace_steps,
+             vol.ctypes.data, mpos.ctypes.data if margins else None,
+             mp.ctypes.data if margins else None, _ptr(trace), trace_steps,
              _ptr(kicks), kick_steps, _ptr(smarg))
     rc = L.oracle_propagate(C.byref(prob.struct), n, C.byref(I), C.byref(O), int(n_threads))
     if rc != 0:
@@ -320,6 +334,57 @@ def nearest(wl, r) -> np.ndarray:
     o = np.zeros(3)
     lib().oracle_nearest(C.byref(prob.struct), r.ctypes.data, o.ctypes.data)
     return o
+
+
+class Decisions:
+    """The oracle's discrete decisions and their margins for one workload
+    (tables copied once, for many queries)."""
+
+    def __init__(self, wl):
+        self._prob = Problem(wl)
+        self._p = C.byref(self._prob.struct)
+        self._L = lib()
+
+    @staticmethod
+    def _r(r):
+        return np.ascontiguousarray(r, dtype=np.float64)
+
+    def lookup(self, r) -> int:
+        r = self._r(r)
+        return int(self._L.oracle_lookup(self._p, r.ctypes.data))
+
+    def geom_margin(self, r) -> float:
+        r = self._r(r)
+        return float(self._L.oracle_geom_margin(self._p, r.ctypes.data))
+
+    def map_margin(self, r) -> float:
+        r = self._r(r)
+        return float(self._L.oracle_map_margin(self._p, r.ctypes.data))
+
+    def break_margin(self, r, pm):
+        """(position margin in m, momentum margin relative to pm)."""
+        r = self._r(r)
+        mp = C.c_double(0.0)
+        mpos = self._L.oracle_break_margin(self._p, r.ctypes.data, float(pm), C.byref(mp))
+        return float(mpos), float(mp.value)
+
+    def bin_margin(self, ibin: int, pm: float) -> float:
+        return float(self._L.oracle_bin_margin(self._p, int(ibin), float(pm)))
+
+    def pbin(self, pm: float) -> int:
+        return int(self._L.oracle_pbin(self._p, float(pm)))
+
+    def nearest(self, r) -> np.ndarray:
+        r = self._r(r)
+        o = np.zeros(3)
+        self._L.oracle_nearest(self._p, r.ctypes.data, o.ctypes.data)
+        return o
+
+    def trilinear(self, r) -> np.ndarray:
+        r = self._r(r)
+        o = np.zeros(3)
+        self._L.oracle_trilinear(self._p, r.ctypes.data, o.ctypes.data)
+        return o
 
 
 def max_threads() -> int:

@@ -342,49 +342,148 @@ int32_t oracle_lookup(const orc_problem *P, const double r[3])
     return -1;
 }
 
-/* Decision margin of the lookup: the smallest distance by which r could move
- * and change whether some box contains it. */
-static double orc_geom_margin(const orc_problem *P, const double r[3])
+/* ---------------------------------------------------------------------- */
+/* Decision margins.  For the tests' boundary-tie rule only: how far the   */
+/* state may move before a discrete decision of the transport loop        */
+/* changes.  A GPU result that parts ways with this oracle at a decision   */
+/* whose margin is below the GPU's own rounding deviation is a tie.        */
+/* Positions are measured in the max-norm over the axes (the largest       */
+/* coordinate change); for convex blocks the in-slice part is Euclidean    */
+/* (see oracle_geom_margin).                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Max-norm distance from r to the nearest point at which box b's
+ * containment of r changes: inside, the nearest face; outside, the largest
+ * per-axis violation (every violated axis must be crossed). */
+static double orc_box_change(const double *bx, const double r[3])
+{
+    double inside = INFINITY, violation = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double dlo = r[a] - bx[2 * a], dhi = bx[2 * a + 1] - r[a];
+        if (dlo >= 0.0 && dhi > 0.0) {
+            double d = dlo < dhi ? dlo : dhi;
+            if (d < inside) inside = d;
+        } else {
+            double v = dlo < 0.0 ? -dlo : -dhi;
+            if (v > violation) violation = v;
+        }
+    }
+    return violation > 0.0 ? violation : inside;
+}
+
+/* Euclidean distance from (x, y) to the segment a-b. */
+static double orc_seg_dist(const double a[2], const double b[2], double x, double y)
+{
+    double ex = b[0] - a[0], ey = b[1] - a[1];
+    double L2 = ex * ex + ey * ey;
+    double t = L2 > 0.0 ? ((x - a[0]) * ex + (y - a[1]) * ey) / L2 : 0.0;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double dx = x - (a[0] + t * ex), dy = y - (a[1] + t * ey);
+    return sqrt(dx * dx + dy * dy);
+}
+
+/* Distance from r to the nearest point at which block pb's containment of
+ * r changes, in the metric max(|dz|, |d(x, y)|): inside, the nearer z face
+ * or the nearest edge line of the slice at r's height (|S_i| / |e_i|, the
+ * in-slice distance to the boundary of a convex polygon); outside, both the
+ * z gap and the in-slice distance to the slice polygon (the nearest edge
+ * segment) must be closed, the latter taken in the slice at the nearer end
+ * when r is outside the z range.  Exact for blocks with vertical faces; for
+ * a face of horizontal slope s per metre of z the true distance is smaller
+ * by at most the factor 1 / (1 + s). */
+static double orc_block_change(const double *pb, const double r[3])
+{
+    double v[4][2], S[4];
+    const int in_z = pb[0] <= r[2] && r[2] < pb[1];
+    double zgap = 0.0, zs = r[2];
+    if (!in_z) {
+        zgap = r[2] < pb[0] ? pb[0] - r[2] : r[2] - pb[1];
+        zs = r[2] < pb[0] ? pb[0] : pb[1];
+    }
+    orc_poly_slice(pb, zs, v);
+    orc_poly_signs(v, r, S);
+    int pos = 1, neg = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (S[i] < 0.0) pos = 0;
+        if (S[i] > 0.0) neg = 0;
+    }
+    if (in_z && (pos || neg)) {
+        double d = r[2] - pb[0];
+        if (pb[1] - r[2] < d) d = pb[1] - r[2];
+        for (int i = 0; i < 4; ++i) {
+            double ex = v[(i + 1) % 4][0] - v[i][0], ey = v[(i + 1) % 4][1] - v[i][1];
+            double e = sqrt(ex * ex + ey * ey);
+            if (e > 0.0 && fabs(S[i]) / e < d) d = fabs(S[i]) / e;
+        }
+        return d;
+    }
+    double dxy = 0.0;
+    if (!(pos || neg)) {
+        dxy = INFINITY;
+        for (int i = 0; i < 4; ++i) {
+            double d = orc_seg_dist(v[i], v[(i + 1) % 4], r[0], r[1]);
+            if (d < dxy) dxy = d;
+        }
+    }
+    return zgap > dxy ? zgap : dxy;
+}
+
+/* Decision margin of the volume lookup at r: the distance r may move before
+ * the lowest-index volume holding it changes.  That happens when r leaves
+ * the volume v it is in, or enters a volume of lower index than v (any
+ * volume when v = -1); volumes of higher index than v cannot change the
+ * answer while r stays in v.  Boxes: exact in the max-norm.  Blocks: as
+ * orc_block_change. */
+double oracle_geom_margin(const orc_problem *P, const double r[3])
 {
     double m = INFINITY;
-    if (P->n_poly > 0) {
-        /* distance to the z faces and, inside the z range, the in-slice
-         * distance |S_i| / |e_i| to each edge line */
-        for (int32_t b = 0; b < P->n_poly; ++b) {
-            const double *pb = P->poly + 18 * b;
-            double d = fabs(r[2] - pb[0]);
-            if (fabs(pb[1] - r[2]) < d) d = fabs(pb[1] - r[2]);
-            if (d < m) m = d;
-            if (!(pb[0] <= r[2] && r[2] < pb[1])) continue;
-            double v[4][2], S[4];
-            orc_poly_slice(pb, r[2], v);
-            orc_poly_signs(v, r, S);
-            for (int i = 0; i < 4; ++i) {
-                double ex = v[(i + 1) % 4][0] - v[i][0], ey = v[(i + 1) % 4][1] - v[i][1];
-                double e = sqrt(ex * ex + ey * ey);
-                if (e > 0.0 && fabs(S[i]) / e < m) m = fabs(S[i]) / e;
-            }
-        }
-        return m;
-    }
-    for (int32_t b = 0; b < P->n_box; ++b) {
-        const double *bx = P->box + 6 * b;
-        double inside_margin = INFINITY, outside_violation = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            double lo = bx[2 * a], hi = bx[2 * a + 1];
-            double dlo = r[a] - lo, dhi = hi - r[a];
-            if (dlo >= 0.0 && dhi > 0.0) {
-                double d = dlo < dhi ? dlo : dhi;
-                if (d < inside_margin) inside_margin = d;
-            } else {
-                double v = dlo < 0.0 ? -dlo : -dhi;
-                if (v > outside_violation) outside_violation = v;
-            }
-        }
-        double mb = outside_violation > 0.0 ? outside_violation : inside_margin;
-        if (mb < m) m = mb;
+    int32_t v = oracle_lookup(P, r);
+    int32_t n = P->n_poly > 0 ? P->n_poly : P->n_box;
+    int32_t last = v >= 0 ? v : n - 1;
+    for (int32_t b = 0; b <= last; ++b) {
+        double d = P->n_poly > 0 ? orc_block_change(P->poly + 18 * b, r)
+                                 : orc_box_change(P->box + 6 * b, r);
+        if (d < m) m = d;
     }
     return m;
+}
+
+/* Margins of the break test at position r with momentum magnitude pm: the
+ * conditions are tested in the order p_min, z_max, x_max, y_max, and the
+ * outcome (continue, or the status of the first condition that holds)
+ * changes only when that condition, or one tested before it, flips; when
+ * none holds, any of the four.  Position distances in metres (max-norm),
+ * the momentum distance relative to pm.  Returns the position margin and
+ * stores the momentum margin in *margin_p.  The step cap is an integer
+ * count and has no margin. */
+double oracle_break_margin(const orc_problem *P, const double r[3], double pm, double *margin_p)
+{
+    double mp = fabs(pm - P->p_min) / pm, mpos = INFINITY, d;
+    if (pm < P->p_min) { *margin_p = mp; return mpos; }
+    d = fabs(r[2] - P->world[2]);
+    if (d < mpos) mpos = d;
+    if (r[2] >= P->world[2]) { *margin_p = mp; return mpos; }
+    d = fabs(fabs(r[0]) - P->world[0]);
+    if (d < mpos) mpos = d;
+    if (fabs(r[0]) >= P->world[0]) { *margin_p = mp; return mpos; }
+    d = fabs(fabs(r[1]) - P->world[1]);
+    if (d < mpos) mpos = d;
+    *margin_p = mp;
+    return mpos;
+}
+
+/* Margin of the momentum-bin decision for bin ibin at magnitude pm,
+ * relative to pm: the distance to the edges at which the bin changes.  The
+ * bin's lower edge counts only above bin 0 and its upper edge only below
+ * bin P-1 (momenta beyond the outer edges are clamped into those bins). */
+double oracle_bin_margin(const orc_problem *P, int32_t ibin, double pm)
+{
+    double d = INFINITY;
+    if (ibin > 0) d = fabs(pm - P->p_edges[ibin]) / pm;
+    if (ibin < P->n_pbin - 1 && fabs(P->p_edges[ibin + 1] - pm) / pm < d)
+        d = fabs(P->p_edges[ibin + 1] - pm) / pm;
+    return d;
 }
 
 /* Momentum bin: e_i <= pm < e_{i+1}; below e_0 -> 0, at or above e_P -> P-1. */
@@ -456,23 +555,36 @@ void oracle_nearest(const orc_problem *P, const double r[3], double B[3])
     B[2] = (double)b[2];
 }
 
-/* Decision margin of the map lookup at r: distance to the faces of the
- * map's domain (the field drops to zero outside it) and, for the nearest-
- * node lookup, to the mid-planes between nodes. */
-static double orc_map_margin(const orc_problem *P, const double r[3])
+/* Decision margin of the map lookup at r (max-norm, metres).  The map
+ * gives zero outside [lo, hi] on every axis, so whether r is inside is a
+ * decision: inside, the distance to the nearest face of the domain;
+ * outside, the largest per-axis violation.  The trilinear interpolant is
+ * continuous across cell faces (no decision there); the nearest-node
+ * lookup also changes its node at the mid-planes between nodes, whose
+ * distance counts for points inside. */
+double oracle_map_margin(const orc_problem *P, const double r[3])
 {
-    double m = INFINITY;
-    if (P->nx <= 0 || P->map == NULL) return m;
+    if (P->nx <= 0 || P->map == NULL) return INFINITY;
     const int32_t n[3] = {P->nx, P->ny, P->nz};
+    double inside = INFINITY, violation = 0.0;
     for (int a = 0; a < 3; ++a) {
-        double d = fabs(r[a] - P->map_lo[a]);
-        if (fabs(P->map_hi[a] - r[a]) < d) d = fabs(P->map_hi[a] - r[a]);
-        if (d < m) m = d;
-        if (P->interp == 1 && r[a] >= P->map_lo[a] && r[a] <= P->map_hi[a]) {
+        double dlo = r[a] - P->map_lo[a], dhi = P->map_hi[a] - r[a];
+        if (dlo >= 0.0 && dhi >= 0.0) {
+            double d = dlo < dhi ? dlo : dhi;
+            if (d < inside) inside = d;
+        } else {
+            double v = dlo < 0.0 ? -dlo : -dhi;
+            if (v > violation) violation = v;
+        }
+    }
+    if (violation > 0.0) return violation;
+    double m = inside;
+    if (P->interp == 1) {
+        for (int a = 0; a < 3; ++a) {
             double sp = (P->map_hi[a] - P->map_lo[a]) / (double)(n[a] - 1);
             double u = (r[a] - P->map_lo[a]) / sp;
-            double f = u - floor(u);              /* mid-plane at f = 0.5 */
-            d = fabs(f - 0.5) * sp;
+            double f = u - floor(u);              /* mid-planes at f = 0.5 */
+            double d = fabs(f - 0.5) * sp;
             if (d < m) m = d;
         }
     }
@@ -501,8 +613,8 @@ static void orc_field(const orc_problem *P, int32_t vol, int32_t variant, const 
 
 /* RK4 step with the field evaluated at every stage position: the field
  * there is the scaled field of the box containing that point plus the map.
- * *margin receives the smallest decision margin (box faces, map) over the
- * three stage points after the first. */
+ * *margin (if not NULL) receives the smallest decision margin (volume
+ * lookup, map) over the three stage points after the first. */
 static void orc_rk4_stages(const orc_problem *P, int32_t variant, const double y_in[6], double q,
                            double h, double y_out[6], double *margin)
 {
@@ -514,10 +626,12 @@ static void orc_rk4_stages(const orc_problem *P, int32_t variant, const double y
     const double c[3] = {0.5 * h, 0.5 * h, h};
     for (int s = 0; s < 3; ++s) {
         for (int a = 0; a < 6; ++a) t[a] = y_in[a] + c[s] * prev[s][a];
-        d = orc_geom_margin(P, t);
-        if (d < *margin) *margin = d;
-        d = orc_map_margin(P, t);
-        if (d < *margin) *margin = d;
+        if (margin) {
+            d = oracle_geom_margin(P, t);
+            if (d < *margin) *margin = d;
+            d = oracle_map_margin(P, t);
+            if (d < *margin) *margin = d;
+        }
         orc_field(P, oracle_lookup(P, t), variant, t, B);
         orc_deriv(t, q, B, ks[s]);
     }
@@ -580,6 +694,8 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
         (in->q[j] != 1 && in->q[j] != -1))
         status = ST_INVALID;
 
+    /* decision margins are formed only when asked for */
+    const int margins = out->margin_pos || out->margin_p || out->step_margin;
     double *sm = NULL;              /* this step's (pos, p) margins */
     while (status == 0) {
         double pm = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
@@ -587,11 +703,8 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
         sm = (out->step_margin && k <= out->trace_steps)
                  ? out->step_margin + ((int64_t)j * (out->trace_steps + 1) + k) * 2 : NULL;
         /* margins of the break test */
-        double d;
-        d = fabs(pm - P->p_min) / pm;               if (d < kp) kp = d;
-        d = fabs(r[2] - P->world[2]);               if (d < kpos) kpos = d;
-        d = fabs(fabs(r[0]) - P->world[0]);         if (d < kpos) kpos = d;
-        d = fabs(fabs(r[1]) - P->world[1]);         if (d < kpos) kpos = d;
+        double d = INFINITY;
+        if (margins) kpos = oracle_break_margin(P, r, pm, &kp);
         if (kpos < mpos) mpos = kpos;
         if (kp < mp) mp = kp;
         if (sm) { sm[0] = kpos; sm[1] = kp; }
@@ -602,7 +715,7 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
         if (k >= P->max_steps) { status = ST_STEPS; break; }
 
         int32_t vol = oracle_lookup(P, r);
-        d = orc_geom_margin(P, r);
+        if (margins) d = oracle_geom_margin(P, r);
         if (d < mpos) mpos = d;
         if (sm && d < sm[0]) sm[0] = d;
         int32_t mat = vol >= 0 ? P->material[vol] : -1;
@@ -610,9 +723,7 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
         int64_t cell = -1;
         if (mat >= 0) {
             ibin = oracle_pbin(P, pm);
-            /* margin to the edges bracketing the chosen bin */
-            d = fabs(pm - P->p_edges[ibin]) / pm;
-            if (fabs(pm - P->p_edges[ibin + 1]) / pm < d) d = fabs(pm - P->p_edges[ibin + 1]) / pm;
+            if (margins) d = oracle_bin_margin(P, ibin, pm);
             if (d < mp) mp = d;
             if (sm && d < sm[1]) sm[1] = d;
             uint32_t ctr[4] = {(uint32_t)mu, (uint32_t)((uint64_t)mu >> 32), (uint32_t)k, 0u};
@@ -645,13 +756,13 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
             int32_t *tr = out->trace + ((int64_t)j * out->trace_steps + k) * 3;
             tr[0] = vol; tr[1] = ibin; tr[2] = (int32_t)cell;
         }
-        d = orc_map_margin(P, r);
+        if (margins) d = oracle_map_margin(P, r);
         if (d < mpos) mpos = d;
         if (sm && d < sm[0]) sm[0] = d;
         double y[6] = {r[0], r[1], r[2], p[0], p[1], p[2]}, yn[6];
         if (P->stage_field) {
             double ms = INFINITY;
-            orc_rk4_stages(P, var, y, q, P->step, yn, &ms);
+            orc_rk4_stages(P, var, y, q, P->step, yn, margins ? &ms : NULL);
             if (ms < mpos) mpos = ms;
             if (sm && ms < sm[0]) sm[0] = ms;
         } else {
@@ -668,8 +779,8 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
     out->status[j] = status;
     out->n_steps[j] = k;
     out->volume[j] = status == ST_INVALID ? -1 : oracle_lookup(P, r);
-    if (status != ST_INVALID) {
-        double d = orc_geom_margin(P, r);     /* the final-volume lookup */
+    if (status != ST_INVALID && margins) {
+        double d = oracle_geom_margin(P, r);  /* the final-volume lookup */
         if (d < mpos) mpos = d;
         if (sm && d < sm[0]) sm[0] = d;
     }
