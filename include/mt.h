@@ -60,7 +60,9 @@ extern "C" {
 
 /* ---- launch forms ------------------------------------------------------ */
 #define MT_MODE_PLAIN       0    /* one lane per muon until it stops */
-#define MT_MODE_PERSISTENT  1    /* resident grid, atomic work queue, compaction */
+#define MT_MODE_PERSISTENT  1    /* resident grid, one atomic work counter; every
+                                    compact_every steps a wavefront with at least
+                                    MT_OPT_REFILL_MIN idle lanes refills them */
 #define MT_MODE_VARIANT_WAVES 2  /* G lanes of a wavefront hold G variants of one muon and
                                     share its random stream, G = the largest power of two
                                     dividing n_variants, at most 64: one Philox block per
@@ -323,11 +325,18 @@ int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons
  *                               momenta in LDS instead of device memory
  *                               (geometries without a field map; ignored with
  *                               one); 0 (default).
+ *   MT_OPT_REFILL_MIN           idle lanes (1..64) a wavefront of the persistent
+ *                               form waits for before it claims new muons from
+ *                               the work counter: fewer keeps more lanes busy,
+ *                               more takes fewer atomic adds; default 8.
+ *                               Setting it drops cached graphs and autotuner
+ *                               choices.
  * Errors: MT_ERR_INVALID_ARG (unknown option or value out of range).
  */
 #define MT_OPT_GUIDE_BITS           1
 #define MT_OPT_ADJOINT_BLOCK        2
 #define MT_OPT_ADJOINT_LDS_HISTORY  3
+#define MT_OPT_REFILL_MIN           4
 int mt_set_option(int32_t option, int64_t value);
 
 /* Thread-local message of the last failing call ("" if none). */

@@ -107,8 +107,10 @@ def load_workload(wl) -> None:
 
 
 OPTIONS = {"guide_bits": _lib.MT_OPT_GUIDE_BITS, "adjoint_block": _lib.MT_OPT_ADJOINT_BLOCK,
-           "adjoint_lds_history": _lib.MT_OPT_ADJOINT_LDS_HISTORY}
-OPTION_DEFAULTS = {"guide_bits": 0, "adjoint_block": 64, "adjoint_lds_history": 0}
+           "adjoint_lds_history": _lib.MT_OPT_ADJOINT_LDS_HISTORY,
+           "refill_min": _lib.MT_OPT_REFILL_MIN}
+OPTION_DEFAULTS = {"guide_bits": 0, "adjoint_block": 64, "adjoint_lds_history": 0,
+                   "refill_min": 8}
 
 
 def set_option(name: str, value: int) -> None:

@@ -100,6 +100,7 @@ struct State {
     int opt_guide_bits = 0;          // 0: automatic
     int opt_adjoint_block = 64;
     int opt_adjoint_lds_history = 0;
+    int opt_refill_min = 8;          // idle lanes before a persistent wavefront refills
 };
 
 State g;
@@ -311,8 +312,9 @@ int enqueue(const mt_params *p, const Call &c, hipStream_t s) {
         if (rc) return rc;
         unsigned long long *queue = reinterpret_cast<unsigned long long *>(g.queue.p);
         MT_HIP(mt::launch_queue_reset(queue, reinterpret_cast<double *>(g.zero_dummy.p), 0, s));
-        const int grid = g.cu_count * mt::persistent_blocks_per_cu(g.T, c.block);
-        MT_HIP(mt::launch_persistent(g.T, c.R, c.io, c.block, grid, c.compact, queue, s));
+        const int grid = g.cu_count * mt::persistent_blocks_per_cu(g.T, c.R, c.block);
+        MT_HIP(mt::launch_persistent(g.T, c.R, c.io, c.block, grid, c.compact, g.opt_refill_min,
+                                     queue, s));
     } else if (p->mode == MT_MODE_VARIANT_WAVES) {
         MT_HIP(mt::launch_variant_waves(g.T, c.R, c.io, c.block, s));
     } else {
@@ -1084,6 +1086,13 @@ int mt_set_option(int32_t option, int64_t value) {
             return fail(MT_ERR_INVALID_ARG, "MT_OPT_ADJOINT_LDS_HISTORY must be 0 or 1");
         g.opt_adjoint_lds_history = (int)value;
         return MT_OK;
+    case MT_OPT_REFILL_MIN:
+        if (value < 1 || value > 64)
+            return fail(MT_ERR_INVALID_ARG, "MT_OPT_REFILL_MIN must be in 1..64");
+        g.opt_refill_min = (int)value;
+        drop_graphs();          // captured persistent launches hold the old value
+        g.tuned.clear();
+        return MT_OK;
     default:
         return fail(MT_ERR_INVALID_ARG, "unknown option %d", option);
     }
@@ -1110,6 +1119,7 @@ void mt_release(void) {
     g.opt_guide_bits = 0;
     g.opt_adjoint_block = 64;
     g.opt_adjoint_lds_history = 0;
+    g.opt_refill_min = 8;
     ++g.version;
 }
 

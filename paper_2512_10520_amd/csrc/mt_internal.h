@@ -107,10 +107,12 @@ struct Tables {
 // Launchers implemented in mt_kernels.hip.
 hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,
                         hipStream_t s);
+// Persistent form: each wavefront refills its idle lanes from the work
+// counter every refill_every steps once at least refill_min lanes are idle.
 hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, int block,
-                             int grid, int compact_every, unsigned long long *queue,
-                             hipStream_t s);
-int persistent_blocks_per_cu(const Tables &T, int block);
+                             int grid, int refill_every, int refill_min,
+                             unsigned long long *queue, hipStream_t s);
+int persistent_blocks_per_cu(const Tables &T, const DevRun &R, int block);
 // Variant-wave form: groups of 2^R.share_shift lanes hold variants of one muon.
 hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &io, int block,
                                hipStream_t s);

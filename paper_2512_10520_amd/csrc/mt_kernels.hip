@@ -185,6 +185,7 @@ __device__ __forceinline__ void load_lane_at(Lane &L, int64_t j, int64_t var, in
     L.slab = -1;
     L.vol = -1;
     L.bvol = -2;
+    L.mcell = -1;
     L.bx = L.by = L.bz = 0.0f;
     L.zlo = INFINITY;
     L.zhi = -INFINITY;
@@ -859,124 +860,77 @@ k_plain(Tables T, DevRun R, DevIO io) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form with block-level stream compaction.  A resident grid pulls
-// batches of blockDim muons from an atomic queue.  The muons of a batch step
-// in lockstep (so lanes of a wave stay at the same z and take the same
-// branches); every `compact` steps the block packs its surviving muons into
-// its lowest lanes through LDS, and waves left without a muon skip the steps
-// until the batch is done, so the issue slots go to busy waves.  When a batch
-// is exhausted the block takes the next one; it exits when the queue is.
-// Results are bit-identical to the plain form: the random stream is keyed by
-// (muon, step), the state moves exactly, and the lookup caches are rebuilt.
+// Persistent form with per-wavefront refill.  A resident grid takes muons
+// from one atomic work counter.  Every `refill_every` steps each wavefront
+// counts its idle lanes (ballot); once at least `refill_min` of its 64 lanes
+// are idle, one lane claims that many muons with a single atomic add and the
+// idle lanes load them (rank of the lane among the idle ones = mbcnt of the
+// ballot), so a wave keeps its lanes busy however uneven the trajectory
+// lengths are, with no block barrier and no state moved between lanes.
+// Lanes of a wave then hold muons at different step counts, which changes
+// nothing: the random stream is keyed by (muon, step) and a lane's lookup
+// caches are reset when it loads a muon.  A wave exits once the counter has
+// passed the last lane and all its lanes are idle, so every wave ends and
+// the grid drains.  Results are bit-identical to the plain form.
 // ---------------------------------------------------------------------------
-struct MoveRec {                // one muon in flight, 64 bytes
-    double x, y, z, px, py, pz;
-    int64_t g;
-    int32_t ibin_slab;          // ibin (low 16 bits) | slab (high 16 bits)
-    int32_t q_vol;              // charge (low 8 bits, signed) | volume + 1 (next 8 bits)
-};
-
-__device__ __forceinline__ void pack_rec(const Lane &L, MoveRec &m) {
-    m.x = L.x;
-    m.y = L.y;
-    m.z = L.z;
-    m.px = L.px;
-    m.py = L.py;
-    m.pz = L.pz;
-    m.g = L.g;
-    m.ibin_slab = (L.ibin & 0xFFFF) | (L.slab << 16);
-    m.q_vol = ((int)L.q & 0xFF) | ((L.vol + 1) << 8);
+__device__ __forceinline__ unsigned long long readfirstlane_u64(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ void unpack_rec(Lane &L, const MoveRec &m, int32_t k, const DevRun &R) {
-    L.x = m.x;
-    L.y = m.y;
-    L.z = m.z;
-    L.px = m.px;
-    L.py = m.py;
-    L.pz = m.pz;
-    L.g = m.g;
-    L.ibin = (int16_t)(m.ibin_slab & 0xFFFF);
-    L.slab = m.ibin_slab >> 16;
-    L.q = (float)(int8_t)(m.q_vol & 0xFF);
-    L.vol = ((m.q_vol >> 8) & 0xFF) - 1;
-    int64_t var = 0, j = L.g;
-    if (R.lanes != R.n) {
-        var = R.lanes <= 0xFFFFFFFFll ? (int64_t)((uint32_t)L.g / (uint32_t)R.n) : L.g / R.n;
-        j = L.g - var * R.n;
-    }
-    L.var = (int32_t)var;
-    L.ph = philox_prefix((uint32_t)j, (uint32_t)((uint64_t)j >> 32), R.key0, R.key1);
-    L.k = k;
-    L.status = MT_ST_RUNNING;
-    L.bvol = -2;                // caches are rebuilt from the moved hints
-    L.mcell = -1;
-    L.zlo = INFINITY;
-    L.zhi = -INFINITY;
-    L.e2lo = INFINITY;
-    L.e2hi = -INFINITY;
+// Occupancy request of the persistent kernels: as in the plain form.
+constexpr int persistent_min_waves(unsigned F) {
+    return plain_min_waves(F);
 }
 
-// Without a map, convex blocks or per-stage fields the compaction state leaves
-// the kernel a few registers above the 96 of 5 waves/SIMD; asking for 5 waves spills three
-// rarely used values and runs the block and scan workloads 7-8 % faster than
-// 4 waves.
 template <unsigned F>     // F never holds kTape
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu((F & (kMap | kPoly | kStages)) ? 1 : 5)))
-k_persistent(Tables T, DevRun R, DevIO io, int compact,
-                                                     unsigned long long *queue) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(persistent_min_waves(F))))
+k_persistent(Tables T, DevRun R, DevIO io, int refill_every, int refill_min,
+             unsigned long long *queue) {
     extern __shared__ __align__(16) char smem[];
-    __shared__ unsigned long long batch_base;
-    __shared__ int wave_count[1024 / kWave];
     const Lds S = stage_tables<(F & kPoly) != 0>(smem, T);
-    MoveRec *recs = reinterpret_cast<MoveRec *>(smem + ((T.lds.bytes + 15) & ~15));
     const StepConst sc = step_const(R);
-    const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
-    const int n_waves = blockDim.x / kWave;
-    for (;;) {
-        if (tid == 0) batch_base = atomicAdd(queue, (unsigned long long)blockDim.x);
-        __syncthreads();
-        const unsigned long long base = batch_base;
-        if (base >= (unsigned long long)R.lanes) break;          // the same for the whole block
-        Lane L;
-        bool active = false;
-        const unsigned long long gg = base + (unsigned long long)tid;
-        if (gg < (unsigned long long)R.lanes) {
-            load_lane(L, (int64_t)gg, io, R);
-            if (L.status == MT_ST_RUNNING) active = true;
-            else store_lane(L, T, S, io);
-        }
-        int n_busy = blockDim.x;        // lanes [0, n_busy) may hold a muon
-        int32_t k_done = 0;             // steps taken by every muon still in the batch
-        for (;;) {
-            if (wave * kWave < n_busy) {
-                for (int c = 0; c < compact; ++c) {
-                    if (active && !advance<F>(L, T, S, R, sc)) {
-                        store_lane(L, T, S, io);
-                        active = false;
+    const unsigned long long lanes = (unsigned long long)R.lanes;
+    Lane L;
+    bool active = false;
+    bool drained = false;       // wave-uniform: the counter has passed the last lane
+    // One loop over steps with the refill as a wave-uniform block every
+    // refill_every passes (a nested refill/step loop pair made the compiler
+    // keep a second copy of the lane's cached map cell: 34 more VGPRs).
+    for (int c = refill_every;; ++c) {
+        if (c >= refill_every) {
+            c = 0;
+            if (!drained) {
+                const uint64_t idle = __ballot(!active);
+                const int n_idle = (int)__popcll(idle);
+                if (n_idle >= refill_min) {
+                    unsigned long long base = 0;
+                    if ((threadIdx.x & (kWave - 1)) == 0)
+                        base = atomicAdd(queue, (unsigned long long)n_idle);
+                    base = readfirstlane_u64(base);
+                    drained = base + (unsigned long long)n_idle >= lanes;
+                    if (!active) {
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+                        const unsigned long long gg = base + rank;
+                        if (gg < lanes) {
+                            load_lane(L, (int64_t)gg, io, R);
+                            if (L.status == MT_ST_RUNNING) active = true;
+                            else store_lane(L, T, S, io);
+                        }
                     }
                 }
             }
-            k_done += compact;
-            // pack the survivors into lanes [0, total)
-            const uint64_t m = __ballot(active);
-            if (lane == 0) wave_count[wave] = (int)__popcll(m);
-            __syncthreads();
-            int before = 0, total = 0;
-            for (int w = 0; w < n_waves; ++w) {
-                const int cnt = wave_count[w];
-                before += (w < wave) ? cnt : 0;
-                total += cnt;
+            if (__ballot(active) == 0) {
+                if (drained) break;
+                c = refill_every - 1;       // every lane is idle: refill again at once
+                continue;
             }
-            const int rank = before + (int)__builtin_amdgcn_mbcnt_hi(
-                                          (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (active) pack_rec(L, recs[rank]);
-            __syncthreads();
-            active = tid < total;
-            if (active) unpack_rec(L, recs[tid], k_done, R);
-            n_busy = total;
-            __syncthreads();            // records and counts are rewritten next round
-            if (total == 0) break;
+        }
+        if (active && !advance<F>(L, T, S, R, sc)) {
+            store_lane(L, T, S, io);
+            active = false;
         }
     }
 }
@@ -1586,38 +1540,35 @@ hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int b
     return hipLaunchKernel(fn, dim3(grid), dim3(block), args, (size_t)T.lds.bytes, s);
 }
 
-static size_t persistent_lds(const Tables &T, int block) {
-    return (size_t)((T.lds.bytes + 15) & ~15) + (size_t)block * sizeof(MoveRec);
-}
+static size_t persistent_lds(const Tables &T) { return (size_t)T.lds.bytes; }
 
 static const void *persistent_fn(unsigned mask) {
     static const auto fns = persistent_kernels(std::make_index_sequence<kFeatures>());
     return fns[mask];
 }
 
-int persistent_blocks_per_cu(const Tables &T, int block) {
+int persistent_blocks_per_cu(const Tables &T, const DevRun &R, int block) {
     int n = 0;
-    // The register footprint of the trace-free inverse-CDF form sets the grid.
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, persistent_fn(T.field.map != nullptr ? kMap : 0u), block, persistent_lds(T, block));
+    const void *fn = persistent_fn(feature_mask(T, R) & ~kTape);
+    if (fn == nullptr) return 1;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, persistent_lds(T));
     if (e != hipSuccess || n < 1) n = 1;
     return n;
 }
 
 hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, int block,
-                             int grid, int compact_every, unsigned long long *queue,
-                             hipStream_t s) {
+                             int grid, int refill_every, int refill_min,
+                             unsigned long long *queue, hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
     Tables t = T;
     DevRun r = R;
     DevIO o = io;
-    int c = compact_every;
+    int c = refill_every, m = refill_min;
     unsigned long long *q = queue;
-    void *args[] = {&t, &r, &o, &c, &q};
+    void *args[] = {&t, &r, &o, &c, &m, &q};
     const void *fn = persistent_fn(feature_mask(T, R) & ~kTape);
     if (fn == nullptr) return hipErrorInvalidValue;     // excluded by argument validation
-    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(block), args, persistent_lds(T, block),
-                           s);
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(block), args, persistent_lds(T), s);
 }
 
 hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &io, int block,
