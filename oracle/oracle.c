@@ -660,7 +660,21 @@ typedef struct {
     float *kicks;                   /* [n][kick_steps][3] (f, tau, phi/2pi) or NULL */
     int32_t kick_steps;
     double *step_margin;            /* [n][trace_steps + 1][2] (pos, p) per step, or NULL */
+    uint64_t *digest;               /* [n] 64-bit FNV-1a hash of every step's (vol, bin,
+                                       cell), or NULL: equal traces, equal digests */
 } orc_out;
+
+/* FNV-1a over the 12 bytes of one step's (vol, bin, cell), little-endian. */
+static uint64_t orc_digest_step(uint64_t h, int32_t vol, int32_t ibin, int32_t cell)
+{
+    const int32_t v[3] = {vol, ibin, cell};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 4; ++b) {
+            h ^= (uint64_t)(((uint32_t)v[a] >> (8 * b)) & 0xFFu);
+            h *= 0x100000001B3ull;
+        }
+    return h;
+}
 
 /* Sampling tables of every histogram h = material * n_pbin + bin. */
 typedef struct {
@@ -697,6 +711,7 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
     /* decision margins are formed only when asked for */
     const int margins = out->margin_pos || out->margin_p || out->step_margin;
     double *sm = NULL;              /* this step's (pos, p) margins */
+    uint64_t digest = 0xCBF29CE484222325ull;
     while (status == 0) {
         double pm = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
         double kpos = INFINITY, kp = INFINITY;
@@ -756,6 +771,7 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
             int32_t *tr = out->trace + ((int64_t)j * out->trace_steps + k) * 3;
             tr[0] = vol; tr[1] = ibin; tr[2] = (int32_t)cell;
         }
+        if (out->digest) digest = orc_digest_step(digest, vol, ibin, (int32_t)cell);
         if (margins) d = oracle_map_margin(P, r);
         if (d < mpos) mpos = d;
         if (sm && d < sm[0]) sm[0] = d;
@@ -786,6 +802,7 @@ static void orc_one(const orc_problem *P, const orc_tables *tab, const orc_in *i
     }
     if (out->margin_pos) out->margin_pos[j] = mpos;
     if (out->margin_p) out->margin_p[j] = mp;
+    if (out->digest) out->digest[j] = digest;
 }
 
 /* Propagate n muons.  Returns 0, or -1 for an empty/oversized histogram, or

@@ -159,3 +159,72 @@ def test_adjoint_lane_independent_of_its_wavefront(torch, name):
     assert np.array_equal(full[:, keep], got[:, keep])
     head, _, _, _ = _gpu_grads(torch, wl, np.arange(77))
     assert np.array_equal(full[:, :77], head)
+
+
+# ---------------------------------------------------------------------------
+# The differentiable design step at its benchmarked size: the diff workload's
+# 10^6 muons with histograms filled with 10^6 pairs each.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def diff_full():
+    return W.make_workload("diff")
+
+
+def test_checkpointed_forward_equals_plain_at_full_size(torch, diff_full):
+    """The checkpointing forward (the kernel that also writes the kick tape)
+    gives the plain launch's final states, statuses, step counts and volumes
+    bit for bit, and its checkpoint m holds the state after 16 m steps: a
+    plain launch capped at 16 m steps stops every muon still running there
+    with exactly that state."""
+    from paper_2512_10520_amd import api
+    wl = diff_full
+    api.load_workload(wl)
+    dm = api.DeviceMuons.from_host(wl.muons)
+    sc = torch.tensor(np.asarray(wl.run.scales, np.float32), device="cuda")
+    spec = api.RunSpec.from_workload(wl)
+    plain = api.propagate(dm, spec, scales=sc)
+    ck = api.propagate(dm, spec, scales=sc, ckpt=True)
+    torch.cuda.synchronize()
+    for k in ("state", "status", "n_steps", "volume"):
+        assert torch.equal(getattr(plain, k), getattr(ck, k)), k
+    ns = plain.n_steps
+    for m in (1, 4, 13):
+        capped = api.RunSpec.from_workload(wl)
+        capped.max_steps = 16 * m
+        c = api.propagate(dm, capped, scales=sc)
+        torch.cuda.synchronize()
+        running = ns > 16 * m                    # still in flight after 16 m steps
+        assert int(running.sum()) > 1000
+        assert torch.equal(c.status[running], torch.full_like(c.status[running], 5))
+        assert torch.equal(c.state[:, running], ck.ckpt[m][:, running]), m
+
+
+def test_design_step_full_size_vs_oracle_fd(torch, diff_full):
+    """The adjoint's 8 scale gradients over all 10^6 muons against the
+    oracle's central differences on common random numbers (Richardson from
+    h = 1e-3 and 5e-4; muons whose decision path differs between a +h and a
+    -h run are left out on both sides), and the input gradients of the first
+    10^3 muons of the same run against per-muon central differences."""
+    wl = diff_full
+    n = len(wl.muons)
+    assert n == 1_000_000
+    idx = np.arange(n)
+    ref, d1, flag = _richardson(lambda h: oracle.fd_scales(wl, idx, h=h), 1e-3)
+    g_x0, gs, status, _ = _gpu_grads(torch, wl, idx, mask=~flag)
+    gs = gs[0]
+    print("adjoint dL/ds", gs, "\nrichardson", ref, "\nfd(h)", d1, "\nflagged", flag.sum())
+    assert flag.mean() < 0.05
+    assert np.all(np.abs(ref) > 1.0)
+    assert np.allclose(gs, ref, rtol=2e-3, atol=0)
+    assert np.all(np.abs(gs - ref) <= np.abs(d1 - ref) + 1e-3 * np.abs(ref))
+    sub = idx[:1000]
+    comps = (0, 1, 3, 4, 5)
+    ref_in, _, flag_in = _richardson(lambda h: oracle.fd_inputs(wl, sub, h=h, comps=comps),
+                                     1e-3)
+    keep = (~flag_in) & (~flag[:1000]) & (status[:1000] == 2)
+    assert keep.sum() > 500
+    for a in comps:
+        r, gg = ref_in[a, keep], g_x0[a, :1000][keep]
+        scale = np.abs(r).max()
+        bad = np.abs(gg - r) > 2e-3 * np.abs(r) + 1e-4 * scale
+        assert not bad.any(), (a, np.flatnonzero(bad)[:5], gg[bad][:5], r[bad][:5])

@@ -137,3 +137,36 @@ def test_fd_common_scale_equals_sum_of_magnet_derivatives():
     g2, _ = oracle.fd_scales(wl, idx[~flag2], h=h)
     assert flag2.mean() < 0.2
     assert abs(total - g2.sum()) <= 2e-3 * max(1.0, abs(total)), (total, g2.sum())
+
+
+def _fnv1a(trace_rows):
+    """64-bit FNV-1a over the little-endian bytes of the (vol, bin, cell) rows."""
+    h = 0xCBF29CE484222325
+    for b in np.ascontiguousarray(trace_rows, dtype="<i4").tobytes():
+        h ^= b
+        h = (h * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_trace_digest_is_the_hash_of_the_whole_trace():
+    """The finite-difference helpers flag a muon when its decision path
+    differs between the +h and -h runs, comparing 64-bit digests of the
+    paths instead of storing them.  The digest must be the FNV-1a hash of
+    every step's (volume, bin, cell), and muons with different paths must get
+    different digests (here: every muon of a short block run differs)."""
+    wl = W.make_workload("block", n_muons=60, n_fill=20_000)
+    r = oracle.propagate(wl, np.arange(60), trace_steps=wl.run.max_steps, digest=True)
+    for j in range(60):
+        k = int(r.n_steps[j])
+        assert int(r.digest[j]) == _fnv1a(r.trace[j, :k]), j
+    assert len(set(r.digest.tolist())) == 60
+    # same path, same digest, whatever else differs: scaling all magnet fields
+    # by 1 + 1e-12 leaves the (vol, bin, cell) path of nearly every muon as is
+    wl2 = W.make_workload("diff", n_muons=40, n_fill=20_000)
+    a = oracle.propagate(wl2, np.arange(40), trace_steps=wl2.run.max_steps, digest=True)
+    b = oracle.propagate(wl2, np.arange(40), trace_steps=wl2.run.max_steps, digest=True,
+                         scales=np.full((1, wl2.geom.n_mag), 1.0 + 1e-12))
+    same = (a.trace == b.trace).all(axis=(1, 2))
+    assert same.sum() >= 35
+    assert np.array_equal(a.digest[same], b.digest[same])
+    assert not np.array_equal(a.state, b.state)
