@@ -279,6 +279,31 @@ int mt_propagate(const mt_params *params, int64_t n, const mt_muons *in, mt_muon
                  mt_result *res, void *hip_stream);
 
 /*
+ * mt_propagate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, kernels and results (bit for bit) as mt_propagate, but the
+ * library workspace this call needs -- the persistent form's work counter
+ * and the tally partial sums -- lives in a fixed device array of
+ * MT_NOALLOC_SCRATCH_BYTES per device instead of library allocations.  The
+ * call makes no hipMalloc or hipFree; it neither captures nor replays a graph
+ * (use_graph must be 0), does not checkpoint (ckpt_every must be 0), and
+ * uses the block and compact_every given (0 = the defaults 256 and 16), not
+ * the autotuner's choices.  The tables must have been loaded (loaders do
+ * allocate).
+ * Limit: with a tally, 256 + 24 * n_variants * min(256, max(1, ceil(n /
+ * 4096))) bytes must fit in MT_NOALLOC_SCRATCH_BYTES, else MT_ERR_LIMIT.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the counter is cleared by a kernel at the start of each
+ * persistent launch; the partial sums are written before they are read):
+ * calls whose device work overlaps on one GPU (different streams) race on
+ * it, so issue them on one stream or wait between them.
+ * Errors: as mt_propagate, plus MT_ERR_LIMIT.
+ */
+#define MT_NOALLOC_SCRATCH_BYTES 1048576   /* 1 MiB */
+int mt_propagate_noalloc(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
+                         mt_result *res, void *hip_stream);
+
+/*
  * Pathwise adjoint of a checkpointed mt_propagate (the differentiable
  * extension suggested in Section "Discussion and Conclusion"): sampled
  * losses, kicks, azimuths, materials, bins and step counts are held fixed.

@@ -20,14 +20,15 @@ MT_INTERP_TRILINEAR, MT_INTERP_NEAREST = 0, 1
 MT_AXIS_LOG_LOSS, MT_AXIS_LOG_SCAT = 1, 2
 MT_OPT_GUIDE_BITS, MT_OPT_ADJOINT_BLOCK, MT_OPT_ADJOINT_LDS_HISTORY = 1, 2, 3
 MT_OPT_REFILL_MIN = 4
+MT_NOALLOC_SCRATCH_BYTES = 1 << 20
 ST_RUNNING, ST_PMIN, ST_ZMAX, ST_XMAX, ST_YMAX, ST_MAXSTEPS, ST_INVALID = range(7)
 CKPT_EVERY = 16
 
 # Names of every entry point the header declares (checked by the CPU tests).
 EXPORTS = ("mt_load_histograms", "mt_load_histograms_ex", "mt_optimal_edges",
            "mt_load_geometry", "mt_load_blocks", "mt_load_field", "mt_propagate",
-           "mt_propagate_backward", "mt_autotune", "mt_set_option", "mt_last_error",
-           "mt_release", "mt_device_info")
+           "mt_propagate_noalloc", "mt_propagate_backward", "mt_autotune", "mt_set_option",
+           "mt_last_error", "mt_release", "mt_device_info")
 
 
 class MtParams(C.Structure):
@@ -75,6 +76,8 @@ def load():
             L.mt_load_field.argtypes = [i32, i32, i32, vp, vp, vp]
             L.mt_propagate.argtypes = [C.POINTER(MtParams), i64, C.POINTER(MtMuons),
                                        C.POINTER(MtMuons), C.POINTER(MtResult), vp]
+            L.mt_propagate_noalloc.argtypes = [C.POINTER(MtParams), i64, C.POINTER(MtMuons),
+                                               C.POINTER(MtMuons), C.POINTER(MtResult), vp]
             L.mt_propagate_backward.argtypes = [C.POINTER(MtParams), i64, C.POINTER(MtMuons),
                                                 C.POINTER(MtResult), vp, vp, vp, vp]
             L.mt_autotune.argtypes = [C.POINTER(MtParams), i64, C.POINTER(MtMuons),

@@ -280,11 +280,13 @@ def _check_result(out: Result, spec: RunSpec, n: int, ckpt: bool, tally: bool) -
 def propagate(muons: DeviceMuons, spec: RunSpec, scales: Optional[torch.Tensor] = None,
               trace_steps: int = 0, n_trace: int = 0, ckpt: bool = False,
               tally: Optional[dict] = None, out: Optional[Result] = None,
-              stream: Optional[torch.cuda.Stream] = None) -> Result:
+              stream: Optional[torch.cuda.Stream] = None, noalloc: bool = False) -> Result:
     """Transport ``muons`` on the GPU (``mt_propagate``).
 
     ``tally`` = dict(z_det=..., r_ap=..., r_scale=...) requests per-variant
     detector-plane tallies.  ``out`` reuses preallocated result tensors.
+    ``noalloc`` calls ``mt_propagate_noalloc`` instead, which allocates no
+    device memory (pass ``out`` as well to allocate nothing here either).
     """
     _check_muons(muons)
     scales = _check_scales(scales, spec)
@@ -302,8 +304,9 @@ def propagate(muons: DeviceMuons, spec: RunSpec, scales: Optional[torch.Tensor] 
     res = MtResult(out.status.data_ptr(), out.n_steps.data_ptr(), out.volume.data_ptr())
     o = MtMuons(*[out.state[a].data_ptr() for a in range(6)], None)
     i = muons.c_struct()
-    check(_lib.load().mt_propagate(C.byref(p), n, C.byref(i), C.byref(o), C.byref(res),
-                                   _stream_handle(stream)))
+    L = _lib.load()
+    fn = L.mt_propagate_noalloc if noalloc else L.mt_propagate
+    check(fn(C.byref(p), n, C.byref(i), C.byref(o), C.byref(res), _stream_handle(stream)))
     return out
 
 

@@ -16,6 +16,11 @@
 
 #include "mt_internal.h"
 
+// Workspace of mt_propagate_noalloc: a file-scope device array, so that the
+// call allocates nothing.  Each device the library runs on holds its own copy
+// until the process ends.
+static __device__ __align__(256) unsigned char scratch[MT_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 using mt::Tables;
@@ -89,7 +94,7 @@ struct State {
     DevBuf cdf, guide, totals, edges2, alias, blk, grid, nodes;
     DevBuf box4, material, bfield, magnet, slab_z, slab_mask;
     DevBuf map;
-    DevBuf queue, partial, scratch, gs_lane, zero_dummy;
+    DevBuf queue, partial, scratch, gs_lane;
     Tables T{};
     int max_material = -1;
     hipStream_t cap_stream = nullptr;
@@ -104,6 +109,14 @@ struct State {
 };
 
 State g;
+
+// Device address of the workspace array `scratch` on each device (looked up
+// once per device; the array's name is no device address in host code).
+// Layout: the persistent form's work counter at byte 0, the tally partial
+// sums from byte kNoallocCounterBytes.
+constexpr size_t kNoallocCounterBytes = 256;
+constexpr int kMaxDevices = 64;
+void *noalloc_addr[kMaxDevices] = {};
 
 int ensure_device() {
     if (g.device < 0) {
@@ -126,21 +139,19 @@ void drop_graphs() {
 }
 
 // Captured graphs hold the addresses of the workspace buffers (the
-// persistent queue, the zeroing dummy and the tally partials) baked into
+// persistent queue and the tally partials) baked into
 // their kernel nodes, and their cache key does not: a graph whose workspace
 // has been reallocated since its capture must never be replayed.  Growing a
 // buffer frees the old one (hipFree waits for the device), then every cached
 // graph is dropped.
 struct WorkspaceAddr {
-    void *queue, *partial, *zero;
+    void *queue, *partial;
 };
 
-WorkspaceAddr workspace_addr() { return {g.queue.p, g.partial.p, g.zero_dummy.p}; }
+WorkspaceAddr workspace_addr() { return {g.queue.p, g.partial.p}; }
 
 void drop_graphs_if_moved(const WorkspaceAddr &before) {
-    if (before.queue != g.queue.p || before.partial != g.partial.p ||
-        before.zero != g.zero_dummy.p)
-        drop_graphs();
+    if (before.queue != g.queue.p || before.partial != g.partial.p) drop_graphs();
 }
 
 void tables_changed() {
@@ -306,12 +317,11 @@ int n_part_blocks(int64_t n) {
 
 // Enqueue transport (+ tallies) on stream s.  With `reset` the persistent
 // queue and the tally outputs are cleared by a kernel first.
-int enqueue(const mt_params *p, const Call &c, hipStream_t s) {
+int enqueue_ws(const mt_params *p, const Call &c, hipStream_t s, unsigned long long *queue,
+               double *partial) {
     if (p->mode == MT_MODE_PERSISTENT) {
-        int rc = g.queue.ensure(sizeof(unsigned long long));
-        if (rc) return rc;
-        unsigned long long *queue = reinterpret_cast<unsigned long long *>(g.queue.p);
-        MT_HIP(mt::launch_queue_reset(queue, reinterpret_cast<double *>(g.zero_dummy.p), 0, s));
+        // the counter is cleared by a kernel (no memset node in a captured graph)
+        MT_HIP(mt::launch_queue_reset(queue, nullptr, 0, s));
         const int grid = g.cu_count * mt::persistent_blocks_per_cu(g.T, c.R, c.block);
         MT_HIP(mt::launch_persistent(g.T, c.R, c.io, c.block, grid, c.compact, g.opt_refill_min,
                                      queue, s));
@@ -322,16 +332,21 @@ int enqueue(const mt_params *p, const Call &c, hipStream_t s) {
     }
     if (p->tally) {
         const int nb = n_part_blocks(c.n);
-        MT_HIP(mt::launch_tally(c.io, c.n, c.n_variants, p->z_det, p->r_ap, p->r_scale,
-                                reinterpret_cast<double *>(g.partial.p), nb, p->tally, s));
+        MT_HIP(mt::launch_tally(c.io, c.n, c.n_variants, p->z_det, p->r_ap, p->r_scale, partial,
+                                nb, p->tally, s));
     }
     return MT_OK;
 }
 
-int prepare_workspace(const mt_params *p, const Call &c) {
+int enqueue(const mt_params *p, const Call &c, hipStream_t s) {
     int rc = g.queue.ensure(sizeof(unsigned long long));
     if (rc) return rc;
-    rc = g.zero_dummy.ensure(16);
+    return enqueue_ws(p, c, s, reinterpret_cast<unsigned long long *>(g.queue.p),
+                      reinterpret_cast<double *>(g.partial.p));
+}
+
+int prepare_workspace(const mt_params *p, const Call &c) {
+    int rc = g.queue.ensure(sizeof(unsigned long long));
     if (rc) return rc;
     if (p->tally) {
         rc = g.partial.ensure((size_t)n_part_blocks(c.n) * c.n_variants * 3 * sizeof(double));
@@ -962,6 +977,49 @@ int mt_propagate(const mt_params *params, int64_t n, const mt_muons *in, mt_muon
     return propagate_impl(params, n, in, out, res, hip_stream, 0, 0, true);
 }
 
+int mt_propagate_noalloc(const mt_params *params, int64_t n, const mt_muons *in, mt_muons *out,
+                         mt_result *res, void *hip_stream) {
+    std::lock_guard<std::mutex> lk(g.mu);
+    Call c;
+    int rc = validate(params, n, in, out, res, false, c);
+    if (rc) return rc;
+    if (params->use_graph)
+        return fail(MT_ERR_INVALID_ARG, "mt_propagate_noalloc captures no graph: use_graph "
+                                        "must be 0");
+    if (params->ckpt_every != 0)
+        return fail(MT_ERR_INVALID_ARG, "mt_propagate_noalloc does not checkpoint");
+    const size_t need =
+        kNoallocCounterBytes +
+        (params->tally ? (size_t)n_part_blocks(c.n) * c.n_variants * 3 * sizeof(double) : 0);
+    if (need > sizeof(scratch))
+        return fail(MT_ERR_LIMIT, "the tally partial sums need %zu bytes of workspace, more than "
+                                  "the %zu of MT_NOALLOC_SCRATCH_BYTES", need, sizeof(scratch));
+    int dev = -1;
+    MT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(MT_ERR_LIMIT, "device index %d beyond %d", dev, kMaxDevices);
+    if (!noalloc_addr[dev]) {       // once per device, with that device current
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MT_ERR_HIP, "hipGetSymbolAddress of the workspace failed: %s",
+                        hipGetErrorString(e));
+        noalloc_addr[dev] = ptr;
+    }
+    char *ws = reinterpret_cast<char *>(noalloc_addr[dev]);
+    unsigned long long *queue = reinterpret_cast<unsigned long long *>(ws);
+    double *partial = reinterpret_cast<double *>(ws + kNoallocCounterBytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (c.lanes == 0) {
+        if (params->tally)
+            MT_HIP(mt::launch_queue_reset(queue, params->tally, (int64_t)params->n_variants * 3,
+                                          s));
+        return MT_OK;
+    }
+    // block and refill interval as given (0: defaults); no autotuner lookup
+    return enqueue_ws(params, c, s, queue, partial);
+}
+
 int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in,
                           const mt_result *res, const double *g_out, double *g_in,
                           double *g_scales, void *hip_stream) {
@@ -1105,7 +1163,7 @@ void mt_release(void) {
     drop_graphs();
     for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.alias, &g.blk, &g.grid, &g.nodes, &g.box4, &g.material, &g.bfield,
                       &g.magnet, &g.slab_z, &g.slab_mask, &g.map, &g.queue, &g.partial,
-                      &g.scratch, &g.gs_lane, &g.zero_dummy})
+                      &g.scratch, &g.gs_lane})
         b->release();
     if (g.cap_stream) {
         (void)hipStreamDestroy(g.cap_stream);
