@@ -1,13 +1,19 @@
 """Benchmark: muon-steps/s of the HIP transport on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config block]
-                    [--no-cpu] [--no-design]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config shield]
+                    [--no-cpu] [--no-extra]
 
 A step is one transport of the whole synthetic batch (all muons to their
 break condition) with every table already resident in HBM.  The default
-workload is the magnetised block: one 5 m iron box in a uniform 1.7 T field,
-95 log momentum bins (0.18-400 GeV) x 100 x 100 histogram cells, 10^6
-power-law muons.  Prints one JSON line.
+workload is the realistic-shaped shield: 40 boxes (magnet yokes, air cores,
+concrete walls) in 8 stations over 30 m, 3 materials x 95 log momentum bins
+(0.18-400 GeV) x 100 x 100 histogram cells, a 100 x 100 x 300 float32 field
+map interpolated trilinearly, 10^7 power-law muons with uneven path lengths;
+the reported form is the faster of the plain and the persistent launch.
+The same default run adds, as extra keys, the magnetised block (10^6
+muons), the batched design scan (64 field variants x 2^17 muons) and the
+differentiable design step (forward with checkpoints + adjoint, 10^6
+muons).  Prints one JSON line.
 """
 import argparse
 import json
@@ -59,6 +65,11 @@ OPS = {
     "block_lookup": {"f64": 40, "int": 3},
 }
 PHILOX = {"mad64": 18, "int": 35}        # the Philox part of a material step
+# The part of a material step that only a material step does (momentum bin,
+# Philox, cell draw and split, jitter and azimuth, kick and rotation: 113):
+# a step outside every material but inside a field does the rest (120).
+SAMPLE = {"f32": 30, "f64": 14, "int": 48, "mad64": 18, "trans": 3}
+OPS["field_step"] = {c: OPS["material"].get(c, 0) - SAMPLE.get(c, 0) for c in CLASS_CYCLES}
 
 
 def share_group(n_variants):
@@ -101,7 +112,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="block", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="shield", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="auto",
                     choices=["auto", "plain", "persistent", "variant_waves"],
                     help="auto: time every form the workload admits and report the fastest "
@@ -114,8 +125,10 @@ def _parse():
     ap.add_argument("--stage-field", action="store_true",
                     help="evaluate the field at every RK4 stage position")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-design", action="store_true")
-    ap.add_argument("--cpu-muons", type=int, default=1_000_000)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="shield: skip the block, design-scan and design-step keys")
+    ap.add_argument("--cpu-muons", type=int, default=0,
+                    help="muons of the oracle sample (0: about 10 s of host time)")
     ap.add_argument("--gather-sweep", action="store_true",
                     help="only measure random-gather rates over a range of table sizes")
     ap.add_argument("--alu-sweep", action="store_true",
@@ -184,96 +197,158 @@ def main():
     from paper_2512_10520_amd import workloads as W
 
     torch.cuda.set_device(0)
-    wl = W.make_workload(args.config)
+    m = measure(api, W, torch, args.config, args.mode, args.sampler, args.interp,
+                args.stage_field, args.steps, args.warmup, other_sampler=True)
+    line = {"metric": METRIC, "value": m["value"], "unit": "muon-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": m["config"], "roofline": m["roofline"]}
+    for k in ("other_sampler", "per_variant_plain_ms"):
+        if k in m:
+            line[k] = m[k]
+    wl = m.pop("_wl")
+
+    if not args.no_extra and args.config == "shield":
+        # the other configured workloads of the same default run
+        blk = measure(api, W, torch, "block", "auto", "cdf", "trilinear", False,
+                      args.steps, args.warmup, other_sampler=True)
+        blk.pop("_wl")
+        if not args.no_gather:
+            blk["gather_ceiling"] = gather_ceiling(torch, blk["value"])
+        line["block"] = blk
+        scan = measure(api, W, torch, "scan", "auto", "cdf", "trilinear", False,
+                       args.steps, args.warmup)
+        scan.pop("_wl")
+        line["scan"] = scan
+        line["design_step"] = design_step(api, W, torch)
+    elif args.config == "block" and not args.no_gather:
+        line["gather_ceiling"] = gather_ceiling(torch, m["value"])
+
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_muons or CPU_MUONS[args.config])
+    print(json.dumps(line), flush=True)
+
+
+# Oracle sample of the cpu_baseline leg: about 10 s on 16 host threads.
+CPU_MUONS = {"tiny": 10_000, "block": 1_000_000, "shield": 500_000, "scan": 500_000,
+             "blocks": 500_000, "logbins": 1_000_000}
+
+
+def measure(api, W, torch, config, mode_arg, sampler, interp, stage_field, steps, warmup,
+            other_sampler=False):
+    """Time one workload: every launch form it admits is autotuned and probed,
+    the fastest is timed over `steps` passes after `warmup` untimed ones."""
+    wl = W.make_workload(config)
     api.load_workload(wl)
     dm = api.DeviceMuons.from_host(wl.muons)
     scales = None
     if wl.run.scales is not None:
         scales = torch.from_numpy(np.ascontiguousarray(wl.run.scales, np.float32)).cuda()
-    use_graph = args.config == "scan"
+    use_graph = config == "scan"
 
-    def spec_for(mode, sampler=args.sampler):
-        return api.RunSpec.from_workload(wl, mode=mode, sampler=sampler, interp=args.interp,
-                                         stage_field=args.stage_field,
+    def spec_for(mode, smp=sampler):
+        return api.RunSpec.from_workload(wl, mode=mode, sampler=smp, interp=interp,
+                                         stage_field=stage_field,
                                          use_graph=use_graph and mode != "plain")
 
-    if args.mode == "auto":
+    if mode_arg == "auto":
         modes = ["plain", "persistent"]
         if wl.run.n_variants > 1:
             modes.append("variant_waves")
     else:
-        modes = [args.mode]
-    tuned = {m: api.autotune(dm, spec_for(m), scales=scales)
-             for m in modes if m != "plain"} or None
-    outs = {m: api.alloc_result(spec_for(m), len(dm), "cuda") for m in modes}
+        modes = [mode_arg]
+    tuned = {md: api.autotune(dm, spec_for(md), scales=scales)
+             for md in modes if md != "plain"} or None
+    outs = {md: api.alloc_result(spec_for(md), len(dm), "cuda") for md in modes}
     probe = {}
-    for m in modes:
-        sp = spec_for(m)
-        for _ in range(max(1, args.warmup)):
-            api.propagate(dm, sp, scales=scales, out=outs[m])
-        _, ms = _time_launches(lambda: api.propagate(dm, sp, scales=scales, out=outs[m]), 2, torch)
-        probe[m] = ms
+    for md in modes:
+        sp = spec_for(md)
+        for _ in range(max(1, warmup)):
+            api.propagate(dm, sp, scales=scales, out=outs[md])
+        _, ms = _time_launches(lambda: api.propagate(dm, sp, scales=scales, out=outs[md]), 2,
+                               torch)
+        probe[md] = ms
     mode = min(probe, key=probe.get)
     sp = spec_for(mode)
     out = outs[mode]
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         api.propagate(dm, sp, scales=scales, out=out)
     torch.cuda.synchronize()
     steps_per_pass = int(out.n_steps.to(torch.int64).sum().item())
-    wall, ev_ms = _time_launches(lambda: api.propagate(dm, sp, scales=scales, out=out),
-                                 args.steps, torch)
-    value = steps_per_pass * args.steps / wall
+    wall, ev_ms = _time_launches(lambda: api.propagate(dm, sp, scales=scales, out=out), steps,
+                                 torch)
+    value = steps_per_pass * steps / wall
     lanes = int(out.n_steps.numel())
     kernel = {"plain": "k_plain", "persistent": "k_persistent",
               "variant_waves": "k_variant_waves"}[mode]
-    traffic = measured_traffic(kernel, args.config)
-    mix = algorithmic_ops(args.config, steps_per_pass, lanes, mode, wl.run.n_variants)
-    alg_ops = sum(mix.values())
+    mix = None
+    if config in ("shield", "blocks"):
+        mix = step_mix(api, spec_for("plain"), scales, wl)
+    ops = algorithmic_ops(config, steps_per_pass, lanes, mode, wl.run.n_variants, mix)
+    alg_ops = sum(ops.values())
     achieved = alg_ops / (ev_ms * 1e-3)
-    peak = alu_peak(mix)
+    peak = alu_peak(ops)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                 "unit": "Tops/s (VALU lane-ops)", "frac": achieved / peak,
-                "traffic": traffic, "kernel": kernel, "kernel_ms": ev_ms,
-                "ops_per_pass": alg_ops,
-                "ops_mix": {c: v / steps_per_pass for c, v in mix.items()},
+                "traffic": measured_traffic(kernel, config), "kernel": kernel,
+                "kernel_ms": ev_ms, "ops_per_pass": alg_ops,
+                "ops_mix": {c: v / steps_per_pass for c, v in ops.items()},
                 "frac_of_base_issue_rate": achieved / VALU_BASE_LANE_OPS}
-    line = {"metric": METRIC, "value": value, "unit": "muon-steps/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic",
-            "config": {"workload": WORKLOADS[args.config], "muons": len(dm),
-                       "lanes": int(out.n_steps.numel()), "muon_steps_per_pass": steps_per_pass,
-                       "mode": mode, "sampler": args.sampler, "interp": args.interp,
-                       "stage_field": args.stage_field, "mode_probe_ms": probe,
-                       "autotune": tuned},
-            "roofline": roofline}
-
-    if args.config == "scan":
-        line["config"]["per_variant_plain_ms"] = per_variant_plain(api, dm, wl, scales, torch)
-
-    if args.config in ("block", "shield", "blocks", "logbins"):
-        other = "alias" if args.sampler == "cdf" else "cdf"
+    if mix is not None:
+        roofline["step_mix_sample"] = mix
+    res = {"_wl": wl, "value": value, "ms_per_step": wall / steps * 1e3,
+           "config": {"workload": WORKLOADS[config], "muons": len(dm), "lanes": lanes,
+                      "muon_steps_per_pass": steps_per_pass, "mode": mode, "sampler": sampler,
+                      "interp": interp, "stage_field": stage_field, "mode_probe_ms": probe,
+                      "autotune": tuned},
+           "roofline": roofline}
+    if config == "scan":
+        res["per_variant_plain_ms"] = per_variant_plain(api, dm, wl, scales, torch)
+    if other_sampler:
+        other = "alias" if sampler == "cdf" else "cdf"
         so = spec_for(mode, other)
         oo = api.alloc_result(so, len(dm), "cuda")
-        for _ in range(max(1, args.warmup)):
+        for _ in range(max(1, warmup)):
             api.propagate(dm, so, scales=scales, out=oo)
         torch.cuda.synchronize()
         st = int(oo.n_steps.to(torch.int64).sum().item())
         _, oms = _time_launches(lambda: api.propagate(dm, so, scales=scales, out=oo),
-                                max(2, min(args.steps, 5)), torch)
-        line["other_sampler"] = {"sampler": other, "mode": mode, "kernel_ms": oms,
-                                 "muon_steps_per_pass": st,
-                                 "muon_steps_per_s": st / (oms * 1e-3)}
+                                max(2, min(steps, 5)), torch)
+        res["other_sampler"] = {"sampler": other, "mode": mode, "kernel_ms": oms,
+                                "muon_steps_per_pass": st,
+                                "muon_steps_per_s": st / (oms * 1e-3)}
+    return res
 
-    if not args.no_gather and args.config == "block":
-        line["gather_ceiling"] = gather_ceiling(torch, value)
 
-    if not args.no_design and args.config == "block":
-        line["design_step"] = design_step(api, W, torch)
-
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_muons)
-    print(json.dumps(line), flush=True)
+def step_mix(api, spec, scales, wl, n_sample=8192):
+    """Fractions of the steps of the first n_sample lanes that are material or
+    not, with a field or not, read from the transport's own per-step trace
+    (volume and momentum bin; bin -1 = no material).  On the shield every
+    step inside the map has a field; on the convex blocks the block's uniform
+    field decides."""
+    import torch
+    n = min(n_sample, len(wl.muons))
+    steps_cap = wl.run.max_steps
+    sample = api.DeviceMuons.from_host(wl.muons.take(np.arange(n)))
+    res = api.propagate(sample, spec, scales=scales, trace_steps=steps_cap, n_trace=n)
+    torch.cuda.synchronize()
+    tr = res.trace[:n].cpu().numpy()
+    ns = res.n_steps[:n].cpu().numpy()
+    k = np.arange(steps_cap)[None, :]
+    taken = k < ns[:, None]
+    vol, mat = tr[:, :, 0], tr[:, :, 1] >= 0
+    if wl.field is not None:
+        field = np.ones_like(mat)
+    else:
+        bb = np.zeros((len(wl.geom.material) + 1, 3), np.float32)
+        if wl.geom.b_box is not None:
+            bb[:-1] = np.asarray(wl.geom.b_box, np.float32)
+        field = (bb[vol] != 0).any(axis=-1)          # vol -1 picks the zero last row
+    tot = max(int(taken.sum()), 1)
+    frac = lambda m: float((taken & m).sum()) / tot
+    return {"lanes": n, "steps": tot, "mat_field": frac(mat & field),
+            "mat_nofield": frac(mat & ~field), "vac_field": frac(~mat & field),
+            "vac_nofield": frac(~mat & ~field)}
 
 
 def gather_rate(torch, nbytes, width, loads=256, reps=3):
@@ -364,13 +439,13 @@ def per_variant_plain(api, dm, wl, scales, torch, reps=2):
     return ms
 
 
-def algorithmic_ops(config, steps, lanes, mode="plain", n_variants=64):
-    """Algorithmic operations of one pass by class (see OPS).  block/scan/diff: the
-    first step of every muon starts in vacuum before the box; tiny: zero
-    field; shield: every step is counted as a material step with a map
-    lookup (an upper bound: the air gaps are vacuum).  The variant-wave form
-    shares the Philox block of a material step among share_group(n_variants)
-    lanes."""
+def algorithmic_ops(config, steps, lanes, mode="plain", n_variants=64, mix=None):
+    """Algorithmic operations of one pass by class (see OPS).  block/scan/diff/
+    logbins: the first step of every muon starts in vacuum before the box;
+    tiny: zero field.  shield and blocks: the material / field split of the
+    steps (`mix`, fractions from step_mix) weights the step kinds; every
+    shield step looks up the map.  The variant-wave form shares the Philox
+    block of a material step among share_group(n_variants) lanes."""
     scale = lambda k, parts: [(k * c, key) for c, key in parts]
     if config in ("block", "scan", "diff", "logbins"):
         n_mat = steps - lanes
@@ -378,12 +453,16 @@ def algorithmic_ops(config, steps, lanes, mode="plain", n_variants=64):
     elif config == "tiny":
         n_mat = steps - lanes
         out = _ops(*scale(n_mat, [(1, "material"), (1, "straight")]), (lanes, "vacuum"))
-    elif config == "blocks":
-        n_mat = steps
-        out = _ops(*scale(steps, [(1, "material"), (1, "block_lookup")]))
     else:
-        n_mat = steps
-        out = _ops(*scale(steps, [(1, "material"), (1, "map")]))
+        if mix is None:
+            mix = {"mat_field": 1.0, "mat_nofield": 0.0, "vac_field": 0.0, "vac_nofield": 0.0}
+        look = "map" if config == "shield" else "block_lookup"
+        n_mat = steps * (mix["mat_field"] + mix["mat_nofield"])
+        out = _ops(*scale(steps * mix["mat_field"], [(1, "material"), (1, look)]),
+                   *scale(steps * mix["mat_nofield"], [(1, "material"), (1, "straight"),
+                                                       (1, look)]),
+                   *scale(steps * mix["vac_field"], [(1, "field_step"), (1, look)]),
+                   *scale(steps * mix["vac_nofield"], [(1, "vacuum"), (1, look)]))
     if mode == "variant_waves":
         keep = 1.0 / share_group(n_variants)
         for c, v in PHILOX.items():

@@ -15,7 +15,9 @@ def test_operation_totals():
     """The class split of each step part adds up to its documented total."""
     totals = {k: sum(v.values()) for k, v in bench.OPS.items()}
     assert totals == {"material": 233, "vacuum": 40, "map": 30, "straight": -84,
-                      "block_lookup": 43}
+                      "block_lookup": 43, "field_step": 120}
+    assert sum(bench.SAMPLE.values()) == 113
+    assert all(v >= 0 for v in bench.OPS["field_step"].values())
     assert sum(bench.PHILOX.values()) == 53
     assert all(bench.OPS["material"][c] >= v for c, v in bench.PHILOX.items())
     assert set().union(*(v.keys() for v in bench.OPS.values())) <= set(bench.CLASS_CYCLES)
@@ -45,6 +47,13 @@ def test_algorithmic_ops_per_workload():
     assert [bench.share_group(v) for v in (1, 3, 8, 12, 64, 96, 128)] == [1, 1, 8, 4, 64, 32, 64]
     assert sum(bench.algorithmic_ops("shield", steps, lanes).values()) == steps * (233 + 30)
     assert sum(bench.algorithmic_ops("blocks", steps, lanes).values()) == steps * (233 + 43)
+    mix = {"mat_field": 0.5, "mat_nofield": 0.25, "vac_field": 0.125, "vac_nofield": 0.125}
+    sh = bench.algorithmic_ops("shield", steps, lanes, mix=mix)
+    assert sum(sh.values()) == pytest.approx(steps * (0.5 * 263 + 0.25 * (233 - 84 + 30) +
+                                                      0.125 * 150 + 0.125 * 70))
+    bl = bench.algorithmic_ops("blocks", steps, lanes, mix=mix)
+    assert sum(bl.values()) == pytest.approx(steps * (0.5 * 276 + 0.25 * (233 - 84 + 43) +
+                                                      0.125 * 163 + 0.125 * 83))
     tiny = bench.algorithmic_ops("tiny", steps, lanes)
     assert sum(tiny.values()) == (steps - lanes) * (233 - 84) + lanes * 40
 

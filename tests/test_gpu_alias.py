@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2512_10520_amd import workloads as W
-from tests._parity import compare, gpu_run, oracle_run
+from tests._parity import compare, gpu_run, map_deltas, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_alias_shield_plain_and_persistent():
     n = len(wl.muons)
     o = oracle_run(wl, np.arange(n), trace_steps=1600)
     g = gpu_run(wl, trace_steps=1600, n_trace=300)
-    s = compare(g, o, trace_rows=300, label="shield alias")
+    s = compare(g, o, trace_rows=300, label="shield alias", **map_deltas(wl))
     gp = gpu_run(wl, mode="persistent", trace_steps=1600, n_trace=300)
     for k in ("state", "status", "n_steps", "volume", "trace"):
         assert np.array_equal(g[k], gp[k]), k

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2512_10520_amd import workloads as W
 from tests import _custom as CU
-from tests._parity import compare, gpu_run, oracle_run
+from tests._parity import compare, gpu_run, map_deltas, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,7 @@ def test_blocks_with_map_and_alias():
     n = len(wl.muons)
     o = oracle_run(wl, np.arange(n), trace_steps=1600)
     g = gpu_run(wl, trace_steps=1600, n_trace=300)
-    s = compare(g, o, trace_rows=300, label="blocks map alias")
+    s = compare(g, o, trace_rows=300, label="blocks map alias", **map_deltas(wl))
     print("blocks map alias", s)
 
 

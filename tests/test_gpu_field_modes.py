@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2512_10520_amd import workloads as W
-from tests._parity import compare, gpu_run, oracle_run
+from tests._parity import compare, gpu_run, map_deltas, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,10 @@ def _with(wl, **kw):
 def test_shield_field_modes(interp, stage):
     wl = _with(W.make_workload("shield", n_muons=2000), interp=interp, stage_field=stage)
     n = len(wl.muons)
-    o = oracle_run(wl, np.arange(n))
-    g = gpu_run(wl)
-    s = compare(g, o, max_tie_frac=0.05, label=f"shield interp={interp} stages={stage}")
+    o = oracle_run(wl, np.arange(n), trace_steps=1600)
+    g = gpu_run(wl, trace_steps=1600, n_trace=300)
+    s = compare(g, o, trace_rows=300, max_tie_frac=0.05,
+                label=f"shield interp={interp} stages={stage}", **map_deltas(wl))
     print("shield", interp, stage, s)
     gp = gpu_run(wl, mode="persistent")
     for k in ("state", "status", "n_steps", "volume"):
@@ -60,7 +61,9 @@ def test_stage_field_box_geometries(name, n):
     for v in range(wl.run.n_variants):
         o = oracle_run(wl, np.arange(n), variant=v, trace_steps=260)
         sel = np.arange(v * n, (v + 1) * n)
-        s = compare(g, o, sel=sel, label=f"{name} stages v={v}")
+        # lanes 0..999 (variant 0) carry a per-step trace
+        s = compare(g, o, sel=sel, trace_rows=1000 if v == 0 else 0,
+                    label=f"{name} stages v={v}")
         print(name, "stages", v, s)
 
 

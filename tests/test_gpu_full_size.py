@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2512_10520_amd import workloads as W
-from tests._parity import compare, gpu_run, oracle_run
+from tests._parity import compare, gpu_run, map_deltas, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -58,5 +58,6 @@ def test_shield_full_size(mode):
     assert n == 10_000_000
     g = gpu_run(wl, mode=mode)
     idx = _sample(n, 1500, 2)
-    s = compare(g, oracle_run(wl, idx), sel=idx, max_tie_frac=0.02, label=f"shield full {mode}")
+    s = compare(g, oracle_run(wl, idx), sel=idx, max_tie_frac=0.02, label=f"shield full {mode}",
+                **map_deltas(wl))
     print("shield full", mode, s)

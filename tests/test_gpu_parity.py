@@ -6,7 +6,7 @@ import pytest
 import oracle
 from paper_2512_10520_amd import workloads as W
 from tests import _custom as CU
-from tests._parity import compare, gpu_run, oracle_run
+from tests._parity import compare, gpu_run, map_deltas, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -60,12 +60,54 @@ def test_shield_prefix_parity_plain_and_persistent():
     n = len(wl.muons)
     o = oracle_run(wl, np.arange(n), trace_steps=1600)
     g = gpu_run(wl, trace_steps=1600, n_trace=500)
-    s = compare(g, o, trace_rows=500, label="shield plain")
+    s = compare(g, o, trace_rows=500, label="shield plain", **map_deltas(wl))
     gp = gpu_run(wl, mode="persistent", trace_steps=1600, n_trace=500)
-    sp = compare(gp, o, trace_rows=500, label="shield persistent")
+    sp = compare(gp, o, trace_rows=500, label="shield persistent", **map_deltas(wl))
     print("shield", s, sp)
     for k in ("state", "status", "n_steps", "volume", "trace"):
         assert np.array_equal(g[k], gp[k]), k
+
+
+@pytest.mark.parametrize("interp,stage,sampler", [(0, 0, 0), (0, 0, 1), (1, 0, 0), (0, 1, 0),
+                                                   (1, 1, 0)],
+                         ids=["trilinear", "alias", "nearest", "stages", "nearest+stages"])
+def test_shield_decision_time_deviation(interp, stage, sampler):
+    """How far the GPU state is from the oracle's at the steps where the
+    decisions are taken, on the shield (field map, 3 materials, paths up to
+    1500 steps) with each field option.  A launch capped at k steps stops
+    every muon still running at step k with its state there, on both sides.
+    Over the muons whose (volume, bin, cell) path agrees with the oracle's up
+    to that step, the largest position and relative momentum deviations at
+    k = 32, 96, ..., 1504 set the map workloads' tie deltas, which must be at
+    least 10x them."""
+    import dataclasses
+    wl = W.make_workload("shield", n_muons=3000)
+    wl = dataclasses.replace(wl, run=dataclasses.replace(wl.run, interp=interp,
+                                                         stage_field=stage, sampler=sampler))
+    n = len(wl.muons)
+    steps = 1600
+    g = gpu_run(wl, trace_steps=steps, n_trace=n)
+    o = oracle_run(wl, np.arange(n), trace_steps=steps)
+    worst_r, worst_p, n_cmp = 0.0, 0.0, 0
+    for k in range(32, 1505, 64):
+        capped = dataclasses.replace(wl, run=dataclasses.replace(wl.run, max_steps=k))
+        gk = gpu_run(capped)
+        om = oracle.propagate(capped, np.arange(n), margins=False)
+        ok = ((g["n_steps"] > k) & (o.n_steps > k) &
+              (g["trace"][:, :k] == o.trace[:, :k]).all(axis=(1, 2)))
+        if not ok.any():
+            continue
+        assert np.all(om.status[ok] == oracle.ST_STEPS) and np.all(gk["status"][ok] == 5)
+        dr = np.linalg.norm(gk["state"][:3, ok] - om.state[:3, ok], axis=0)
+        pm = np.linalg.norm(om.state[3:, ok], axis=0)
+        dp = np.linalg.norm(gk["state"][3:, ok] - om.state[3:, ok], axis=0) / pm
+        worst_r, worst_p = max(worst_r, dr.max()), max(worst_p, dp.max())
+        n_cmp += int(ok.sum())
+    print(f"shield interp={interp} stages={stage} sampler={sampler} decision-time deviation: "
+          f"{n_cmp} (muon, step) pairs, max |dr| {worst_r:.3g} m, max rel dp {worst_p:.3g}")
+    assert n_cmp > 20_000
+    d = map_deltas(wl)
+    assert 10 * worst_r <= d["delta_pos"] and 10 * worst_p <= d["delta_p"]
 
 
 def test_scan_variants_parity():
