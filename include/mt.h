@@ -60,9 +60,10 @@ extern "C" {
 
 /* ---- launch forms ------------------------------------------------------ */
 #define MT_MODE_PLAIN       0    /* one lane per muon until it stops */
-#define MT_MODE_PERSISTENT  1    /* resident grid, one atomic work counter; every
-                                    compact_every steps a wavefront with at least
-                                    MT_OPT_REFILL_MIN idle lanes refills them */
+#define MT_MODE_PERSISTENT  1    /* compacting form: step-synchronised passes of
+                                    compact_every steps over the whole batch; the
+                                    muons still running after a pass are compacted
+                                    into the list the next pass runs on */
 #define MT_MODE_VARIANT_WAVES 2  /* G lanes of a wavefront hold G variants of one muon and
                                     share its random stream, G = the largest power of two
                                     dividing n_variants, at most 64: one Philox block per
@@ -234,7 +235,9 @@ typedef struct mt_params {
     const float *scales;      /* device [n_variants][n_mag] or NULL (all 1) */
     int32_t  mode;            /* MT_MODE_PLAIN / MT_MODE_PERSISTENT / MT_MODE_VARIANT_WAVES */
     int32_t  block;           /* threads per block, multiple of 64 in [64, 1024]; 0 = default */
-    int32_t  compact_every;   /* persistent: steps between refills, >= 1; 0 = default */
+    int32_t  compact_every;   /* persistent: steps per pass, >= 1 (0 = 128); raised to
+                                 ceil((max_steps + 1) / 64) so there are at most 64
+                                 passes; >= max_steps + 1: one pass */
     int32_t  use_graph;       /* persistent and variant-wave forms: capture the launch once
                                  as a hipGraph and replay */
     /* differentiable form */
@@ -269,8 +272,9 @@ typedef struct mt_params {
  * With use_graph, the first call for a given argument set captures
  * queue reset + transport (+ tallies) into a hipGraph that later identical
  * calls replay; changing any pointer or parameter captures a new graph.
- * Library-owned workspaces (the persistent form's work counter, the tally
- * and scale-gradient partial sums, the adjoint's segment history) are shared
+ * Library-owned workspaces (the compacting form's counters and survivor
+ * lists, the tally and scale-gradient partial sums, the adjoint's segment
+ * history) are shared
  * by every call: calls whose device work may overlap (on different streams)
  * race on them, so issue such calls on one stream or wait between them.
  * Errors: MT_ERR_NOT_LOADED, MT_ERR_INVALID_ARG, MT_ERR_SHAPE, MT_ERR_HIP.
@@ -286,9 +290,10 @@ int mt_propagate(const mt_params *params, int64_t n, const mt_muons *in, mt_muon
  * and the tally partial sums -- lives in a fixed device array of
  * MT_NOALLOC_SCRATCH_BYTES per device instead of library allocations.  The
  * call makes no hipMalloc or hipFree; it neither captures nor replays a graph
- * (use_graph must be 0), does not checkpoint (ckpt_every must be 0), and
- * uses the block and compact_every given (0 = the defaults 256 and 16), not
- * the autotuner's choices.  The tables must have been loaded (loaders do
+ * (use_graph must be 0), does not checkpoint (ckpt_every must be 0), uses
+ * the block given (0 = 256), not the autotuner's choice, and runs the
+ * compacting form (MT_MODE_PERSISTENT) as one pass over the whole step range
+ * (the survivor lists of several passes would need 112 bytes per lane).  The tables must have been loaded (loaders do
  * allocate).
  * Limit: with a tally, 256 + 24 * n_variants * min(256, max(1, ceil(n /
  * 4096))) bytes must fit in MT_NOALLOC_SCRATCH_BYTES, else MT_ERR_LIMIT.
@@ -323,9 +328,9 @@ int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in
                           double *g_scales, void *hip_stream);
 
 /*
- * Pick block size and refill interval of the persistent form by timing
- * candidate launches of this exact call (blocks {64,128,256,512} x refill
- * intervals {4,8,16,32,64,128}) on the caller's stream; for
+ * Pick block size and pass length of the compacting form by timing
+ * candidate launches of this exact call (blocks {64,128,256,512} x steps
+ * per pass {32,64,128,256,512, the whole step range}) on the caller's stream; for
  * MT_MODE_VARIANT_WAVES only the block size is tuned (best_compact gets 0).
  * Outputs are overwritten (every candidate writes identical bits).  The
  * choice is returned and remembered for later calls with compact_every = 0
@@ -350,18 +355,11 @@ int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons
  *                               momenta in LDS instead of device memory
  *                               (geometries without a field map; ignored with
  *                               one); 0 (default).
- *   MT_OPT_REFILL_MIN           idle lanes (1..64) a wavefront of the persistent
- *                               form waits for before it claims new muons from
- *                               the work counter: fewer keeps more lanes busy,
- *                               more takes fewer atomic adds; default 8.
- *                               Setting it drops cached graphs and autotuner
- *                               choices.
  * Errors: MT_ERR_INVALID_ARG (unknown option or value out of range).
  */
 #define MT_OPT_GUIDE_BITS           1
 #define MT_OPT_ADJOINT_BLOCK        2
 #define MT_OPT_ADJOINT_LDS_HISTORY  3
-#define MT_OPT_REFILL_MIN           4
 int mt_set_option(int32_t option, int64_t value);
 
 /* Thread-local message of the last failing call ("" if none). */

@@ -19,7 +19,6 @@ MT_SAMPLER_CDF, MT_SAMPLER_ALIAS = 0, 1
 MT_INTERP_TRILINEAR, MT_INTERP_NEAREST = 0, 1
 MT_AXIS_LOG_LOSS, MT_AXIS_LOG_SCAT = 1, 2
 MT_OPT_GUIDE_BITS, MT_OPT_ADJOINT_BLOCK, MT_OPT_ADJOINT_LDS_HISTORY = 1, 2, 3
-MT_OPT_REFILL_MIN = 4
 MT_NOALLOC_SCRATCH_BYTES = 1 << 20
 ST_RUNNING, ST_PMIN, ST_ZMAX, ST_XMAX, ST_YMAX, ST_MAXSTEPS, ST_INVALID = range(7)
 CKPT_EVERY = 16

@@ -107,10 +107,8 @@ def load_workload(wl) -> None:
 
 
 OPTIONS = {"guide_bits": _lib.MT_OPT_GUIDE_BITS, "adjoint_block": _lib.MT_OPT_ADJOINT_BLOCK,
-           "adjoint_lds_history": _lib.MT_OPT_ADJOINT_LDS_HISTORY,
-           "refill_min": _lib.MT_OPT_REFILL_MIN}
-OPTION_DEFAULTS = {"guide_bits": 0, "adjoint_block": 64, "adjoint_lds_history": 0,
-                   "refill_min": 8}
+           "adjoint_lds_history": _lib.MT_OPT_ADJOINT_LDS_HISTORY}
+OPTION_DEFAULTS = {"guide_bits": 0, "adjoint_block": 64, "adjoint_lds_history": 0}
 
 
 def set_option(name: str, value: int) -> None:
@@ -341,8 +339,8 @@ def propagate_backward(muons: DeviceMuons, spec: RunSpec, fwd: Result, g_out: to
 
 def autotune(muons: DeviceMuons, spec: RunSpec, scales=None, out: Optional[Result] = None,
              stream=None):
-    """Time the candidate (block, refill interval) pairs of the persistent
-    form -- or the block sizes of the variant-wave form when ``spec.mode`` is
+    """Time the candidate (block, steps per pass) pairs of the compacting
+    form (mode "persistent") -- or the block sizes of the variant-wave form when ``spec.mode`` is
     "variant_waves" -- on this call and remember the fastest (``mt_autotune``)."""
     _check_muons(muons)
     scales = _check_scales(scales, spec)

@@ -94,7 +94,7 @@ struct State {
     DevBuf cdf, guide, totals, edges2, alias, blk, grid, nodes;
     DevBuf box4, material, bfield, magnet, slab_z, slab_mask;
     DevBuf map;
-    DevBuf queue, partial, scratch, gs_lane;
+    DevBuf queue, partial, scratch, gs_lane, lists;
     Tables T{};
     int max_material = -1;
     hipStream_t cap_stream = nullptr;
@@ -105,7 +105,6 @@ struct State {
     int opt_guide_bits = 0;          // 0: automatic
     int opt_adjoint_block = 64;
     int opt_adjoint_lds_history = 0;
-    int opt_refill_min = 8;          // idle lanes before a persistent wavefront refills
 };
 
 State g;
@@ -145,13 +144,14 @@ void drop_graphs() {
 // buffer frees the old one (hipFree waits for the device), then every cached
 // graph is dropped.
 struct WorkspaceAddr {
-    void *queue, *partial;
+    void *queue, *partial, *lists;
 };
 
-WorkspaceAddr workspace_addr() { return {g.queue.p, g.partial.p}; }
+WorkspaceAddr workspace_addr() { return {g.queue.p, g.partial.p, g.lists.p}; }
 
 void drop_graphs_if_moved(const WorkspaceAddr &before) {
-    if (before.queue != g.queue.p || before.partial != g.partial.p) drop_graphs();
+    if (before.queue != g.queue.p || before.partial != g.partial.p || before.lists != g.lists.p)
+        drop_graphs();
 }
 
 void tables_changed() {
@@ -201,7 +201,7 @@ struct Call {
     mt::DevRun R{};
     mt::DevIO io{};
     int block = 256;
-    int compact = 16;
+    int compact = 128;
     int n_variants = 1;
     int64_t n = 0, lanes = 0;
 };
@@ -275,7 +275,7 @@ int validate(const mt_params *p, int64_t n, const mt_muons *in, const mt_muons *
     c.n_variants = p->n_variants;
     c.lanes = n * p->n_variants;
     c.block = p->block ? p->block : 256;
-    c.compact = p->compact_every ? p->compact_every : 16;
+    c.compact = p->compact_every ? p->compact_every : 128;
     mt::DevRun &R = c.R;
     R.h = p->step_m;
     R.sampler = p->sampler;
@@ -315,16 +315,45 @@ int n_part_blocks(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(nb, 256));
 }
 
-// Enqueue transport (+ tallies) on stream s.  With `reset` the persistent
-// queue and the tally outputs are cleared by a kernel first.
-int enqueue_ws(const mt_params *p, const Call &c, hipStream_t s, unsigned long long *queue,
-               double *partial) {
+// Passes of the compacting form: steps per pass S (compact_every, at least
+// (max_steps + 1) / kMaxPasses) and their number.  Passes 0 .. P-2 end at
+// (p + 1) S <= max_steps, the last one runs to the step cap.
+constexpr int kMaxPasses = 64;
+
+void pass_plan(int max_steps, int compact, int *S, int *P) {
+    const int64_t span = (int64_t)max_steps + 1;
+    int64_t st = std::max<int64_t>(compact, (span + kMaxPasses - 1) / kMaxPasses);
+    *S = (int)std::min<int64_t>(st, span);
+    *P = (int)((span + *S - 1) / *S);
+}
+
+// Enqueue transport (+ tallies) on stream s.  `counters` holds kMaxPasses
+// 64-bit survivor counts, one per pass of the compacting form (cleared by a
+// kernel here, never by a memset node in a captured graph); `lists` the two
+// lists of survivor slots (lanes int64 each), or nullptr: then the
+// compacting form runs the whole step range as one pass.
+int enqueue_ws(const mt_params *p, const Call &c, hipStream_t s, unsigned long long *counters,
+               char *lists, double *partial) {
     if (p->mode == MT_MODE_PERSISTENT) {
-        // the counter is cleared by a kernel (no memset node in a captured graph)
-        MT_HIP(mt::launch_queue_reset(queue, nullptr, 0, s));
-        const int grid = g.cu_count * mt::persistent_blocks_per_cu(g.T, c.R, c.block);
-        MT_HIP(mt::launch_persistent(g.T, c.R, c.io, c.block, grid, c.compact, g.opt_refill_min,
-                                     queue, s));
+        int S = 0, P = 1;
+        pass_plan(p->max_steps, lists ? c.compact : p->max_steps + 1, &S, &P);
+        if (P > 1)
+            MT_HIP(mt::launch_queue_reset(counters, reinterpret_cast<double *>(counters), P, s));
+        for (int pp = 0; pp < P; ++pp) {
+            mt::PassArgs a{};
+            a.k_begin = pp * S;
+            a.max_steps = p->max_steps;
+            mt::DevRun r = c.R;                 // the pass ends at its own step cap
+            if (pp < P - 1) r.max_steps = (pp + 1) * S;
+            a.n_in = pp == 0 ? nullptr : counters + pp - 1;
+            a.n_out = counters + pp;
+            if (P > 1) {
+                int64_t *l = reinterpret_cast<int64_t *>(lists);
+                if (pp > 0) a.in = l + ((pp - 1) & 1) * c.lanes;
+                a.out = l + (pp & 1) * c.lanes;
+            }
+            MT_HIP(mt::launch_pass(g.T, r, c.io, c.block, a, s));
+        }
     } else if (p->mode == MT_MODE_VARIANT_WAVES) {
         MT_HIP(mt::launch_variant_waves(g.T, c.R, c.io, c.block, s));
     } else {
@@ -339,15 +368,21 @@ int enqueue_ws(const mt_params *p, const Call &c, hipStream_t s, unsigned long l
 }
 
 int enqueue(const mt_params *p, const Call &c, hipStream_t s) {
-    int rc = g.queue.ensure(sizeof(unsigned long long));
-    if (rc) return rc;
+    int S = 0, P = 1;
+    if (p->mode == MT_MODE_PERSISTENT) pass_plan(p->max_steps, c.compact, &S, &P);
     return enqueue_ws(p, c, s, reinterpret_cast<unsigned long long *>(g.queue.p),
+                      P > 1 ? reinterpret_cast<char *>(g.lists.p) : nullptr,
                       reinterpret_cast<double *>(g.partial.p));
 }
 
 int prepare_workspace(const mt_params *p, const Call &c) {
-    int rc = g.queue.ensure(sizeof(unsigned long long));
+    int rc = g.queue.ensure(kMaxPasses * sizeof(unsigned long long));
     if (rc) return rc;
+    if (p->mode == MT_MODE_PERSISTENT) {
+        int S = 0, P = 1;
+        pass_plan(p->max_steps, c.compact, &S, &P);
+        if (P > 1 && (rc = g.lists.ensure(2 * (size_t)c.lanes * sizeof(int64_t)))) return rc;
+    }
     if (p->tally) {
         rc = g.partial.ensure((size_t)n_part_blocks(c.n) * c.n_variants * 3 * sizeof(double));
         if (rc) return rc;
@@ -1016,8 +1051,9 @@ int mt_propagate_noalloc(const mt_params *params, int64_t n, const mt_muons *in,
                                           s));
         return MT_OK;
     }
-    // block and refill interval as given (0: defaults); no autotuner lookup
-    return enqueue_ws(params, c, s, queue, partial);
+    // block as given (0: default); no autotuner lookup; the persistent form
+    // runs as one pass (its survivor lists would need 112 bytes per lane)
+    return enqueue_ws(params, c, s, queue, nullptr, partial);
 }
 
 int mt_propagate_backward(const mt_params *params, int64_t n, const mt_muons *in,
@@ -1071,9 +1107,9 @@ int mt_autotune(const mt_params *params, int64_t n, const mt_muons *in, mt_muons
                                         "MT_MODE_VARIANT_WAVES launches");
     hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
     const int blocks[] = {64, 128, 256, 512};
-    const bool waves = params->mode == MT_MODE_VARIANT_WAVES;   // no refill interval to tune
+    const bool waves = params->mode == MT_MODE_VARIANT_WAVES;   // no pass length to tune
     const std::vector<int> compacts =
-        waves ? std::vector<int>{16} : std::vector<int>{4, 8, 16, 32, 64, 128};
+        waves ? std::vector<int>{16} : std::vector<int>{32, 64, 128, 256, 512, 1 << 30};
     hipEvent_t e0, e1;
     MT_HIP(hipEventCreate(&e0));
     MT_HIP(hipEventCreate(&e1));
@@ -1144,13 +1180,6 @@ int mt_set_option(int32_t option, int64_t value) {
             return fail(MT_ERR_INVALID_ARG, "MT_OPT_ADJOINT_LDS_HISTORY must be 0 or 1");
         g.opt_adjoint_lds_history = (int)value;
         return MT_OK;
-    case MT_OPT_REFILL_MIN:
-        if (value < 1 || value > 64)
-            return fail(MT_ERR_INVALID_ARG, "MT_OPT_REFILL_MIN must be in 1..64");
-        g.opt_refill_min = (int)value;
-        drop_graphs();          // captured persistent launches hold the old value
-        g.tuned.clear();
-        return MT_OK;
     default:
         return fail(MT_ERR_INVALID_ARG, "unknown option %d", option);
     }
@@ -1163,7 +1192,7 @@ void mt_release(void) {
     drop_graphs();
     for (DevBuf *b : {&g.cdf, &g.guide, &g.totals, &g.edges2, &g.alias, &g.blk, &g.grid, &g.nodes, &g.box4, &g.material, &g.bfield,
                       &g.magnet, &g.slab_z, &g.slab_mask, &g.map, &g.queue, &g.partial,
-                      &g.scratch, &g.gs_lane})
+                      &g.scratch, &g.gs_lane, &g.lists})
         b->release();
     if (g.cap_stream) {
         (void)hipStreamDestroy(g.cap_stream);
@@ -1177,7 +1206,6 @@ void mt_release(void) {
     g.opt_guide_bits = 0;
     g.opt_adjoint_block = 64;
     g.opt_adjoint_lds_history = 0;
-    g.opt_refill_min = 8;
     ++g.version;
 }
 

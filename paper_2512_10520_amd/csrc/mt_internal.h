@@ -104,15 +104,26 @@ struct Tables {
     LdsLayout lds;
 };
 
+// One pass of the compacting form: the items (the launch's lanes, or the
+// output slots listed by the previous pass) step from k_begin up to the
+// DevRun::max_steps of the launch;
+// every muon is stored in its output slot, and the slots of those still
+// running there are appended to `out` for the next pass.
+struct PassArgs {
+    int32_t k_begin;             // first step of the pass (its last is DevRun::max_steps)
+    int32_t max_steps;           // the real step cap
+    const unsigned long long *n_in;   // slots listed by the previous pass, or nullptr: all lanes
+    const int64_t *in;           // [*n_in] output slots to resume
+    unsigned long long *n_out;   // slots appended by this pass (zeroed beforehand)
+    int64_t *out;                // [lanes] at most
+};
+
 // Launchers implemented in mt_kernels.hip.
 hipError_t launch_plain(const Tables &T, const DevRun &R, const DevIO &io, int block,
                         hipStream_t s);
-// Persistent form: each wavefront refills its idle lanes from the work
-// counter every refill_every steps once at least refill_min lanes are idle.
-hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, int block,
-                             int grid, int refill_every, int refill_min,
-                             unsigned long long *queue, hipStream_t s);
-int persistent_blocks_per_cu(const Tables &T, const DevRun &R, int block);
+// One pass of the compacting form (see PassArgs).
+hipError_t launch_pass(const Tables &T, const DevRun &R, const DevIO &io, int block,
+                       const PassArgs &P, hipStream_t s);
 // Variant-wave form: groups of 2^R.share_shift lanes hold variants of one muon.
 hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &io, int block,
                                hipStream_t s);

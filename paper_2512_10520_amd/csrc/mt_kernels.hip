@@ -68,6 +68,12 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 __device__ __forceinline__ uint4 philox_step(const PhiloxPrefix &P, uint32_t step, uint32_t k0,
                                              uint32_t k1) {
+    // The round keys k + r (Weyl increment) are formed here, by scalar adds,
+    // at every call: hoisted out of a step loop they would be 16 more
+    // long-lived scalar registers, which the step loops do not have (they
+    // were spilled to vector-register lanes and read back with v_readlane,
+    // a vector instruction, plus a wait, for every round of every step).
+    __asm__ volatile("" : "+s"(k0), "+s"(k1));
     // round 1: only the product with the step word varies
     const uint64_t pb1 = (uint64_t)kMulB * step;
     const uint32_t n0_1 = (uint32_t)(pb1 >> 32) ^ P.c1;
@@ -860,77 +866,98 @@ k_plain(Tables T, DevRun R, DevIO io) {
 }
 
 // ---------------------------------------------------------------------------
-// Persistent form with per-wavefront refill.  A resident grid takes muons
-// from one atomic work counter.  Every `refill_every` steps each wavefront
-// counts its idle lanes (ballot); once at least `refill_min` of its 64 lanes
-// are idle, one lane claims that many muons with a single atomic add and the
-// idle lanes load them (rank of the lane among the idle ones = mbcnt of the
-// ballot), so a wave keeps its lanes busy however uneven the trajectory
-// lengths are, with no block barrier and no state moved between lanes.
-// Lanes of a wave then hold muons at different step counts, which changes
-// nothing: the random stream is keyed by (muon, step) and a lane's lookup
-// caches are reset when it loads a muon.  A wave exits once the counter has
-// passed the last lane and all its lanes are idle, so every wave ends and
-// the grid drains.  Results are bit-identical to the plain form.
+// Compacting form: step-synchronised passes.
+//
+// The whole batch advances in passes of S steps: pass p takes every muon
+// still in flight from step p S to step (p + 1) S (the last pass runs to the
+// step cap), and the muons still running there are compacted into the list
+// the next pass runs on, so every wave of a pass starts full.
+// Muons in flight at any time are within S steps of each other, i.e. at
+// about the same depth in z, so the part of a field map they read is a slab
+// of the map, not the whole map: its lines stay in the caches instead of
+// streaming from HBM.  A wave of a pass runs at most S steps, so lanes
+// whose muon stops early idle for at most S steps.
+//
+// One lane per item as in the plain form (item i of the pass: lane i of the
+// launch in the first pass, entry i of the previous pass's list after it).
+// Every lane stores its muon in its output slot as the plain form does; a
+// muon still running at the pass's end is stored there too (status running, its step
+// count, its state) and its slot is appended to the list, with one atomic
+// add per wavefront (ballot, then each lane at the wave's base + the
+// survivors of lower lanes) and no block barrier, so a wave that is done
+// leaves at once.  The next pass resumes the muon from its output slot.
+// Results are bit-identical to the plain form: the random stream is keyed by
+// (muon, step), the state moves exactly, and the lookup caches are rebuilt
+// when a muon is resumed.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long readfirstlane_u64(unsigned long long v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((unsigned long long)hi << 32) | lo;
-}
 
-// Occupancy request of the persistent kernels: as in the plain form.
-constexpr int persistent_min_waves(unsigned F) {
-    return plain_min_waves(F);
+// Lane state of the muon of output slot g resumed at step k from that slot.
+__device__ __forceinline__ void resume_lane(Lane &L, int64_t g, int32_t k, const DevIO &io,
+                                            const DevRun &R) {
+    int64_t var = 0, j = g;
+    if (R.lanes != R.n) {
+        var = R.lanes <= 0xFFFFFFFFll ? (int64_t)((uint32_t)g / (uint32_t)R.n) : g / R.n;
+        j = g - var * R.n;
+    }
+    load_lane_at(L, j, var, g, io, R);      // charge, Philox prefix, caches reset
+    L.x = io.ox[g];
+    L.y = io.oy[g];
+    L.z = io.oz[g];
+    L.px = io.opx[g];
+    L.py = io.opy[g];
+    L.pz = io.opz[g];
+    L.k = k;
+    L.status = MT_ST_RUNNING;
 }
 
 template <unsigned F>     // F never holds kTape
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(persistent_min_waves(F))))
-k_persistent(Tables T, DevRun R, DevIO io, int refill_every, int refill_min,
-             unsigned long long *queue) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(plain_min_waves(F))))
+k_pass(Tables T, DevRun R, DevIO io, PassArgs P) {
     extern __shared__ __align__(16) char smem[];
+    // items of this pass: the launch's lanes (first pass) or the survivors
+    // of the previous pass, whose count that pass left in memory
+    const int64_t items = P.n_in ? (int64_t)*P.n_in : R.lanes;
+    if ((int64_t)blockIdx.x * blockDim.x >= items) return;     // the whole block
     const Lds S = stage_tables<(F & kPoly) != 0>(smem, T);
     const StepConst sc = step_const(R);
-    const unsigned long long lanes = (unsigned long long)R.lanes;
-    Lane L;
-    bool active = false;
-    bool drained = false;       // wave-uniform: the counter has passed the last lane
-    // One loop over steps with the refill as a wave-uniform block every
-    // refill_every passes (a nested refill/step loop pair made the compiler
-    // keep a second copy of the lane's cached map cell: 34 more VGPRs).
-    for (int c = refill_every;; ++c) {
-        if (c >= refill_every) {
-            c = 0;
-            if (!drained) {
-                const uint64_t idle = __ballot(!active);
-                const int n_idle = (int)__popcll(idle);
-                if (n_idle >= refill_min) {
-                    unsigned long long base = 0;
-                    if ((threadIdx.x & (kWave - 1)) == 0)
-                        base = atomicAdd(queue, (unsigned long long)n_idle);
-                    base = readfirstlane_u64(base);
-                    drained = base + (unsigned long long)n_idle >= lanes;
-                    if (!active) {
-                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-                        const unsigned long long gg = base + rank;
-                        if (gg < lanes) {
-                            load_lane(L, (int64_t)gg, io, R);
-                            if (L.status == MT_ST_RUNNING) active = true;
-                            else store_lane(L, T, S, io);
-                        }
-                    }
-                }
-            }
-            if (__ballot(active) == 0) {
-                if (drained) break;
-                c = refill_every - 1;       // every lane is idle: refill again at once
-                continue;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool parked = false;        // still running at the pass's end: goes on in the next pass
+    int64_t slot = 0;           // its output slot
+    if (i < items) {
+        Lane L;
+        if (P.n_in) resume_lane(L, P.in[i], P.k_begin, io, R);
+        else load_lane(L, i, io, R);
+        // The pass ends where R.max_steps says (the host sets it to the
+        // pass's last step, or to the step cap in the last pass), so the
+        // step loop is the plain form's: a muon that meets no other break
+        // condition at the pass's end stops with the step-cap status, and
+        // is parked here if the real cap lies beyond.  The break test it
+        // passed there is the one the next pass repeats at the same step.
+        if (L.status == MT_ST_RUNNING) {
+            for (;;) {
+                if (!advance<F>(L, T, S, R, sc)) break;
             }
         }
-        if (active && !advance<F>(L, T, S, R, sc)) {
-            store_lane(L, T, S, io);
-            active = false;
+        if (L.status == MT_ST_MAXSTEPS && L.k < P.max_steps) {
+            parked = true;
+            slot = L.g;
+            L.status = MT_ST_RUNNING;
+        }
+        store_lane(L, T, S, io);            // status running if parked
+    }
+    // wave-aggregated append of the survivors' slots (no block barrier: a
+    // wave that is done leaves at once and frees its registers for the next)
+    const uint64_t m = __ballot(parked);
+    if (m) {
+        unsigned long long base = 0;
+        if ((threadIdx.x & (kWave - 1)) == 0)
+            base = atomicAdd(P.n_out, (unsigned long long)__popcll(m));
+        base = __builtin_amdgcn_readfirstlane((uint32_t)base) |
+               ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32);
+        if (parked) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            P.out[base + rank] = slot;
         }
     }
 }
@@ -1491,7 +1518,7 @@ static const void *plain_kernel() {
 template <unsigned F>
 static const void *persistent_kernel() {
     if constexpr (valid_mask(F) && !(F & kTape))
-        return reinterpret_cast<const void *>(&k_persistent<F>);
+        return reinterpret_cast<const void *>(&k_pass<F>);
     else return nullptr;
 }
 
@@ -1547,28 +1574,20 @@ static const void *persistent_fn(unsigned mask) {
     return fns[mask];
 }
 
-int persistent_blocks_per_cu(const Tables &T, const DevRun &R, int block) {
-    int n = 0;
-    const void *fn = persistent_fn(feature_mask(T, R) & ~kTape);
-    if (fn == nullptr) return 1;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, persistent_lds(T));
-    if (e != hipSuccess || n < 1) n = 1;
-    return n;
-}
-
-hipError_t launch_persistent(const Tables &T, const DevRun &R, const DevIO &io, int block,
-                             int grid, int refill_every, int refill_min,
-                             unsigned long long *queue, hipStream_t s) {
+hipError_t launch_pass(const Tables &T, const DevRun &R, const DevIO &io, int block,
+                       const PassArgs &P, hipStream_t s) {
     if (R.lanes == 0) return hipSuccess;
+    // sized for every lane (the survivors of a pass are at most that many);
+    // blocks past the pass's items exit before staging their tables
+    const unsigned grid = (unsigned)((R.lanes + block - 1) / block);
     Tables t = T;
     DevRun r = R;
     DevIO o = io;
-    int c = refill_every, m = refill_min;
-    unsigned long long *q = queue;
-    void *args[] = {&t, &r, &o, &c, &m, &q};
+    PassArgs pa = P;
+    void *args[] = {&t, &r, &o, &pa};
     const void *fn = persistent_fn(feature_mask(T, R) & ~kTape);
     if (fn == nullptr) return hipErrorInvalidValue;     // excluded by argument validation
-    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(block), args, persistent_lds(T), s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(block), args, persistent_lds(T), s);
 }
 
 hipError_t launch_variant_waves(const Tables &T, const DevRun &R, const DevIO &io, int block,

@@ -153,12 +153,10 @@ def test_geometry_and_field_validation(L):
 def test_option_validation(L):
     for opt, bad in ((_lib.MT_OPT_GUIDE_BITS, -1), (_lib.MT_OPT_GUIDE_BITS, 17),
                      (_lib.MT_OPT_ADJOINT_BLOCK, 96), (_lib.MT_OPT_ADJOINT_BLOCK, 512),
-                     (_lib.MT_OPT_ADJOINT_LDS_HISTORY, 2), (_lib.MT_OPT_REFILL_MIN, 0),
-                     (_lib.MT_OPT_REFILL_MIN, 65), (99, 0)):
+                     (_lib.MT_OPT_ADJOINT_LDS_HISTORY, 2), (4, 8), (99, 0)):
         assert L.mt_set_option(opt, bad) == -1, (opt, bad)
     for opt, good in ((_lib.MT_OPT_GUIDE_BITS, 0), (_lib.MT_OPT_ADJOINT_BLOCK, 64),
-                      (_lib.MT_OPT_ADJOINT_LDS_HISTORY, 0), (_lib.MT_OPT_REFILL_MIN, 64),
-                      (_lib.MT_OPT_REFILL_MIN, 8)):
+                      (_lib.MT_OPT_ADJOINT_LDS_HISTORY, 0)):
         assert L.mt_set_option(opt, good) == 0
 
 

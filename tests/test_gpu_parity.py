@@ -137,6 +137,21 @@ def test_scan_variants_plain_launch():
             print("scan plain", v, var, s)
 
 
+@pytest.mark.parametrize("steps_per_pass", [7, 32, 128, 1000, 4000])
+def test_compacting_passes_match_plain_bitwise(steps_per_pass):
+    """The compacting form in passes of 7 (raised to the 64-pass minimum of
+    32), 32, 128, 1000 and 4000 (one pass) steps gives the plain launch's
+    outputs and per-step traces bit for bit on the shield, whose paths
+    (up to 1500 steps) cross many pass boundaries, with tallies."""
+    wl = W.make_workload("shield", n_muons=20_000, n_fill=100_000)
+    tally = {"z_det": 30.0, "r_ap": 1.0, "r_scale": 0.01}
+    a = gpu_run(wl, mode="plain", trace_steps=1600, n_trace=300, tally=tally)
+    b = gpu_run(wl, mode="persistent", compact_every=steps_per_pass, trace_steps=1600,
+                n_trace=300, tally=tally)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), (k, steps_per_pass)
+
+
 def test_persistent_matches_plain_bitwise():
     wl = W.make_workload("block", n_muons=50_000)
     a = gpu_run(wl, mode="plain")

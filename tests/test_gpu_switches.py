@@ -4,9 +4,7 @@ mt_set_option sets the inverse-CDF guide resolution at table load
 (MT_OPT_GUIDE_BITS: a coarser guide leaves wider brackets to the probe), keeps
 the adjoint's segment history in LDS instead of device memory
 (MT_OPT_ADJOINT_LDS_HISTORY) and sets the adjoint's block size
-(MT_OPT_ADJOINT_BLOCK), and sets how many idle lanes a wavefront of the
-persistent form waits for before it refills (MT_OPT_REFILL_MIN).  Each must
-give the default's bits."""
+(MT_OPT_ADJOINT_BLOCK).  Each must give the default's bits."""
 import numpy as np
 import pytest
 
@@ -79,17 +77,3 @@ def test_adjoint_switches_give_the_same_gradients(env):
         hx, hs = _grads(torch, wl, 3000)
     assert np.array_equal(gx, hx), env
     assert np.array_equal(gs, hs), env
-
-
-@pytest.mark.parametrize("refill_min", [1, 33, 64])
-def test_refill_threshold_does_not_change_results(refill_min):
-    """Persistent launches that refill a wavefront at 1, 33 or 64 idle lanes
-    give the plain launch's bits, traces included (the shield: uneven
-    trajectory lengths, so waves refill at many different steps)."""
-    wl = W.make_workload("shield", n_muons=20_000, n_fill=100_000)
-    ref = gpu_run(wl, mode="plain", trace_steps=400, n_trace=200)
-    with _option(refill_min=refill_min):
-        got = gpu_run(wl, mode="persistent", trace_steps=400, n_trace=200, block=128,
-                      compact_every=8)
-    for k in KEYS + ("trace",):
-        assert np.array_equal(ref[k], got[k]), (refill_min, k)
