@@ -117,6 +117,14 @@ def _parse():
                     choices=["auto", "plain", "persistent", "variant_waves"],
                     help="auto: time every form the workload admits and report the fastest "
                          "(variant_waves: workloads with several field variants)")
+    ap.add_argument("--block", type=int, default=0,
+                    help="threads per block of the timed form (0: autotuned / default)")
+    ap.add_argument("--compact", type=int, default=0,
+                    help="persistent form: steps per pass (0: autotuned); with --block and a "
+                         "fixed --mode the autotuner is skipped (for profiling runs)")
+    ap.add_argument("--design-only", action="store_true",
+                    help="time only the differentiable design step (forward with checkpoints "
+                         "and adjoint, 10^6 muons) and print it")
     ap.add_argument("--sampler", default="cdf", choices=["cdf", "alias"],
                     help="histogram-cell sampler of the timed pass (the other one is timed "
                          "beside it on the block workload)")
@@ -134,6 +142,8 @@ def _parse():
     ap.add_argument("--alu-sweep", action="store_true",
                     help="measure SIMD cycles per wave-level VALU instruction for five "
                          "instruction kinds (libmt_gbench.so) and exit")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip timing the other sampler beside the timed pass")
     ap.add_argument("--no-gather", action="store_true",
                     help="skip the gather-ceiling microbenchmark")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -197,8 +207,12 @@ def main():
     from paper_2512_10520_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.design_only:
+        print(json.dumps({"design_step": design_step(api, W, torch)}), flush=True)
+        return
     m = measure(api, W, torch, args.config, args.mode, args.sampler, args.interp,
-                args.stage_field, args.steps, args.warmup, other_sampler=True)
+                args.stage_field, args.steps, args.warmup, other_sampler=not args.no_other,
+                block=args.block, compact=args.compact)
     line = {"metric": METRIC, "value": m["value"], "unit": "muon-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -235,7 +249,7 @@ CPU_MUONS = {"tiny": 10_000, "block": 1_000_000, "shield": 500_000, "scan": 500_
 
 
 def measure(api, W, torch, config, mode_arg, sampler, interp, stage_field, steps, warmup,
-            other_sampler=False):
+            other_sampler=False, block=0, compact=0):
     """Time one workload: every launch form it admits is autotuned and probed,
     the fastest is timed over `steps` passes after `warmup` untimed ones."""
     wl = W.make_workload(config)
@@ -249,7 +263,8 @@ def measure(api, W, torch, config, mode_arg, sampler, interp, stage_field, steps
     def spec_for(mode, smp=sampler):
         return api.RunSpec.from_workload(wl, mode=mode, sampler=smp, interp=interp,
                                          stage_field=stage_field,
-                                         use_graph=use_graph and mode != "plain")
+                                         use_graph=use_graph and mode != "plain",
+                                         block=block, compact_every=compact)
 
     if mode_arg == "auto":
         modes = ["plain", "persistent"]
@@ -257,8 +272,9 @@ def measure(api, W, torch, config, mode_arg, sampler, interp, stage_field, steps
             modes.append("variant_waves")
     else:
         modes = [mode_arg]
+    pinned = block > 0 and mode_arg != "auto"
     tuned = {md: api.autotune(dm, spec_for(md), scales=scales)
-             for md in modes if md != "plain"} or None
+             for md in modes if md != "plain" and not pinned} or None
     outs = {md: api.alloc_result(spec_for(md), len(dm), "cuda") for md in modes}
     probe = {}
     for md in modes:
@@ -279,7 +295,7 @@ def measure(api, W, torch, config, mode_arg, sampler, interp, stage_field, steps
                                  torch)
     value = steps_per_pass * steps / wall
     lanes = int(out.n_steps.numel())
-    kernel = {"plain": "k_plain", "persistent": "k_persistent",
+    kernel = {"plain": "k_plain", "persistent": "k_pass",
               "variant_waves": "k_variant_waves"}[mode]
     mix = None
     if config in ("shield", "blocks"):
