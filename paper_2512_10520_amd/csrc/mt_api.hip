@@ -774,9 +774,23 @@ int mt_load_geometry(int32_t n_box, const double *box, const int32_t *material, 
 }
 
 // Convex blocks (Section "Simulation", item 1).  Each block is stored as
-// kBlockRec doubles: z_lo, z_hi, 1 / (z_hi - z_lo), 0, the quad at z_lo as
-// (x, y) x 4, and the per-vertex change (top - bottom) x 4, so that the
-// slice at height z is bottom + t (top - bottom), t = (z - z_lo) / (z_hi - z_lo).
+// kBlockRec doubles: z_lo, z_hi, 1 / (z_hi - z_lo), m (below), the quad at
+// z_lo as (x, y) x 4, and the per-vertex change (top - bottom) x 4, so that
+// the slice at height z is bottom + t (top - bottom), t = (z - z_lo) / (z_hi -
+// z_lo).
+//
+// m = sigma tau lets a lane keep the block it found at the previous step:
+// a point whose edge products S_i of block b's slice all satisfy
+// sigma S_i > tau (sigma = +-1 the vertex order) is inside b and, when m is
+// not 0, inside no block of lower index, so the lookup's answer is b
+// without testing the others.  m is not 0 only if every lower-index block
+// whose z range meets b's lies, over the common z range, on the outer side
+// of one edge line of b up to tau / 2: then any point of it has
+// sigma S_i <= tau for that edge (S_i is affine in the point at fixed z, so
+// its largest value over a slice is at a vertex, and quadratic in z along a
+// vertex, so its largest value over the z range is at an end or at the
+// stationary point).  tau = 1e-9 L^2 (L the largest extent of the blocks)
+// is far above the rounding of S_i and far below any distance that matters.
 // A uniform grid over the blocks' bounding box lists, per cell, the blocks
 // whose bounding box (grown by a small margin) meets the cell: the spatial
 // hashing that prunes candidates before the sign test.
@@ -794,6 +808,36 @@ static int quad_orientation(const double q[8]) {
         sgn = si;
     }
     return sgn;
+}
+
+// Edge product S_i of the slice at height z of the block with record r at
+// the point (px, py), in the kernel's formula.
+static double block_edge_product(const double *r, int i, double px, double py, double z) {
+    const double t = (z - r[0]) * r[2];
+    const int j = (i + 1) & 3;
+    const double vix = t * r[12 + 2 * i] + r[4 + 2 * i], viy = t * r[13 + 2 * i] + r[5 + 2 * i];
+    const double vjx = t * r[12 + 2 * j] + r[4 + 2 * j], vjy = t * r[13 + 2 * j] + r[5 + 2 * j];
+    return (vjx - vix) * (py - viy) - (vjy - viy) * (px - vix);
+}
+
+// Largest value over [z0, z1] of sigma S_i of block rb at vertex k of block ra.
+static double max_edge_product_on_vertex(const double *rb, int i, double sigma, const double *ra,
+                                         int k, double z0, double z1) {
+    auto f = [&](double z) {
+        const double ta = (z - ra[0]) * ra[2];
+        const double px = ta * ra[12 + 2 * k] + ra[4 + 2 * k];
+        const double py = ta * ra[13 + 2 * k] + ra[5 + 2 * k];
+        return sigma * block_edge_product(rb, i, px, py, z);
+    };
+    const double fa = f(z0), fm = f(0.5 * (z0 + z1)), fb = f(z1);
+    double best = std::max(fa, std::max(fm, fb));
+    // quadratic through the three samples: f = fm + b u + a u^2, u in [-1, 1]
+    const double a = 0.5 * (fa + fb) - fm, b = 0.5 * (fb - fa);
+    if (a < 0.0) {
+        const double u = -b / (2.0 * a);
+        if (u > -1.0 && u < 1.0) best = std::max(best, fm + b * u + a * u * u);
+    }
+    return best;
 }
 
 int mt_load_blocks(int32_t n, const double *block, const int32_t *material, const float *b_box,
@@ -863,6 +907,32 @@ int mt_load_blocks(int32_t n, const double *block, const int32_t *material, cons
         mag[b] = m;
         bf[b] = b_box ? make_float4(b_box[3 * b], b_box[3 * b + 1], b_box[3 * b + 2], 0.f)
                       : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // m of every block (see above): lower-index blocks separated by an edge line
+    {
+        double L = 0.0;
+        for (int a = 0; a < 3; ++a) L = std::max(L, hi[a] - lo[a]);
+        const double tau = 1e-9 * L * L;
+        for (int b = 0; b < n; ++b) {
+            double *rb = rec.data() + (size_t)mt::kBlockRec * b;
+            const double sigma = (double)quad_orientation(block + 18 * b + 2);
+            bool ok = true;
+            for (int a = 0; a < b && ok; ++a) {
+                const double *ra = rec.data() + (size_t)mt::kBlockRec * a;
+                const double z0 = std::max(ra[0], rb[0]), z1 = std::min(ra[1], rb[1]);
+                if (!(z0 < z1)) continue;            // half-open z ranges that do not meet
+                bool sep = false;
+                for (int i = 0; i < 4 && !sep; ++i) {
+                    double worst = -INFINITY;
+                    for (int k = 0; k < 4; ++k)
+                        worst = std::max(worst, max_edge_product_on_vertex(rb, i, sigma, ra, k,
+                                                                           z0, z1));
+                    sep = worst <= 0.5 * tau;
+                }
+                ok = sep;
+            }
+            rb[3] = ok ? sigma * tau : 0.0;
+        }
     }
     // Grid: about kGridCells roughly cubic cells over the bounding box grown by
     // a margin far above the rounding of a cell index.

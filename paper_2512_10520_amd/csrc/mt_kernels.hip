@@ -291,9 +291,37 @@ __device__ __forceinline__ bool in_block(const Lds &S, int b, double x, double y
     return pos || neg;
 }
 
-// Lowest-index block holding the lane's position: the grid cell's candidate
-// mask, then the sign test, lowest index first.
+// Is (x, y, z) inside block b with every edge product beyond the block's
+// margin (sigma S_i > tau, record word 3 = sigma tau, 0 = never)?  Then no
+// block of lower index holds the point (the loader checked that each of
+// them lies on the outer side of one of b's edge lines up to tau / 2).
+__device__ __forceinline__ bool in_block_clear(const Lds &S, int b, double x, double y, double z) {
+    const double *r = S.blk + kBlockRec * b;
+    const double m = r[3];
+    if (m == 0.0 || !(r[0] <= z && z < r[1])) return false;
+    const double t = (z - r[0]) * r[2];
+    double vx[4], vy[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        vx[i] = fma(t, r[12 + 2 * i], r[4 + 2 * i]);
+        vy[i] = fma(t, r[13 + 2 * i], r[5 + 2 * i]);
+    }
+    const double m2 = m * m;
+    bool clear = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (i + 1) & 3;
+        const double si = (vx[j] - vx[i]) * (y - vy[i]) - (vy[j] - vy[i]) * (x - vx[i]);
+        clear = clear & (si * m > m2);
+    }
+    return clear;
+}
+
+// Lowest-index block holding the lane's position: the block of the previous
+// step if the point is clear inside it, else the grid cell's candidate mask,
+// then the sign test, lowest index first.
 __device__ __forceinline__ int locate_block(Lane &L, const Tables &T, const Lds &S) {
+    if (L.vol >= 0 && in_block_clear(S, L.vol, L.x, L.y, L.z)) return L.vol;
     const DevGeom &G = T.geom;
     const double u = (L.x - G.g0[0]) * G.ginv[0];
     const double v = (L.y - G.g0[1]) * G.ginv[1];

@@ -79,6 +79,35 @@ def test_block_lookup_on_faces_and_overlaps():
     assert expect[4] == 0 and expect[5] == 1 and expect[6] == 1
 
 
+def test_block_lookup_cache_along_paths():
+    """A lane keeps the block of its previous step when its point is clear
+    inside it and no lower-index block can reach into it (checked at load).
+    Straight vacuum paths through overlapping, face-sharing and twisted
+    blocks: the per-step volume of every muon equals the oracle's lookup
+    (which tests every block, lowest index first) at every step, and the
+    final volumes and states agree."""
+    rect = lambda x0, x1, y0, y1: [x0, y0, x1, y0, x1, y1, x0, y1]
+    blocks = [
+        [0.0, 2.0] + rect(-1.0, 0.2, -1.0, 1.0) + rect(-1.0, 0.5, -1.0, 1.0),    # 0: reaches into 1
+        [0.5, 2.5] + rect(0.0, 1.0, -1.0, 1.0) + rect(0.0, 1.0, -1.0, 1.0),      # 1: overlapped by 0
+        [0.0, 2.5] + rect(1.0, 2.0, -1.0, 1.0) + rect(1.0, 2.0, -1.0, 1.0),      # 2: shares x = 1 with 1
+        [0.0, 2.5] + rect(-2.0, -1.0, -1.0, 1.0) + [-2.0, -0.8, -1.2, -1.0, -1.0, 1.0, -2.0, 0.9],  # 3: twisted
+    ]
+    geom = CU.geometry(None, [-1, -1, -1, -1], world=(3.0, 3.0, 2.6), poly=blocks)
+    rng = np.random.default_rng(11)
+    n = 3000
+    x0, y0 = rng.uniform(-2.2, 2.2, n), rng.uniform(-1.2, 1.2, n)
+    px, py = rng.normal(0.0, 0.4, n), rng.normal(0.0, 0.2, n)
+    mu = CU.muons(x0, y0, -0.005, px, py, 10.0, 1)
+    wl = CU.workload(CU.flat_histograms(), geom, mu, max_steps=300, p_min=0.1)
+    g = gpu_run(wl, trace_steps=300, n_trace=n)
+    o = oracle_run(wl, np.arange(n), trace_steps=300)
+    s = compare(g, o, trace_rows=n, label="block cache paths")
+    print("block cache paths", s)
+    vols = np.unique(g["trace"][:, :, 0])
+    assert {0, 1, 2, 3} <= set(vols.tolist())
+
+
 def test_blocks_reject_unsupported_forms():
     import torch
     from paper_2512_10520_amd import api
