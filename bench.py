@@ -563,13 +563,14 @@ HBM_PEAK_GBS = 8000.0
 
 def adjoint_bytes(steps, lanes, n_mag):
     """Device-memory bytes the checkpoint-and-replay adjoint has to move.  Per
-    muon-step: the 16-byte kick record read twice (segment replay and reverse
+    muon-step: the 12-byte kick record read twice (segment replay and reverse
     sweep), the 12-byte pre-kick momentum written in the replay and read in
-    the reverse sweep, and a 48-byte FP64 checkpoint read once per 16 steps.
+    the reverse sweep, and a 48-byte FP64 checkpoint read once per 16 steps
+    (the step's volume is found again by the replay and kept in LDS).
     Per lane: the output gradient read and the input gradient written (48
     bytes each), step count, status and charge (16), and one FP64 scale
     gradient per magnet written."""
-    return steps * (2 * 16 + 2 * 12 + 48 / 16) + lanes * (48 + 48 + 16 + 8 * n_mag)
+    return steps * (2 * 12 + 2 * 12 + 48 / 16) + lanes * (48 + 48 + 16 + 8 * n_mag)
 
 
 def cpu_baseline(wl, n_muons):

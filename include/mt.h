@@ -243,7 +243,7 @@ typedef struct mt_params {
     /* differentiable form */
     int32_t  ckpt_every;      /* 0 = off, or 16: checkpoint (r, p) every 16 steps */
     double  *ckpt;            /* device [ceil(max_steps/16)][6][lanes] */
-    float   *tape;            /* device [max_steps][lanes][4]: local kick (3) + volume bits */
+    float   *tape;            /* device [max_steps][lanes][3]: local kick of every step */
     /* per-step trace for the first n_trace lanes */
     int32_t *trace;           /* device [n_trace][trace_steps][3] = volume, bin, cell; or NULL */
     int64_t  n_trace;

@@ -164,7 +164,7 @@ class Result:
     volume: torch.Tensor         # [lanes] int32
     trace: Optional[torch.Tensor] = None   # [n_trace][trace_steps][3] int32
     ckpt: Optional[torch.Tensor] = None    # [n_ckpt][6][lanes] float64
-    tape: Optional[torch.Tensor] = None    # [max_steps][lanes][4] float32
+    tape: Optional[torch.Tensor] = None    # [max_steps][lanes][3] float32
     tally: Optional[torch.Tensor] = None   # [n_variants][3] float64
 
 
@@ -242,7 +242,7 @@ def alloc_result(spec: RunSpec, n: int, device, trace_steps=0, n_trace=0, ckpt=F
     if ckpt:
         n_ck = max(1, -(-spec.max_steps // _lib.CKPT_EVERY))
         r.ckpt = torch.empty((n_ck, 6, lanes), dtype=torch.float64, device=dev)
-        r.tape = torch.empty((max(1, spec.max_steps), lanes, 4), dtype=torch.float32, device=dev)
+        r.tape = torch.empty((max(1, spec.max_steps), lanes, 3), dtype=torch.float32, device=dev)
     if tally:
         r.tally = torch.empty((spec.n_variants, 3), dtype=torch.float64, device=dev)
     return r
@@ -268,9 +268,9 @@ def _check_result(out: Result, spec: RunSpec, n: int, ckpt: bool, tally: bool) -
         if (out.ckpt.shape[0] < n_ck or tuple(out.ckpt.shape[1:]) != (6, lanes) or
                 out.ckpt.dtype != torch.float64):
             raise ValueError(f"ckpt must be float64 [>={n_ck}][6][{lanes}]")
-        if (out.tape.shape[0] < spec.max_steps or tuple(out.tape.shape[1:]) != (lanes, 4) or
+        if (out.tape.shape[0] < spec.max_steps or tuple(out.tape.shape[1:]) != (lanes, 3) or
                 out.tape.dtype != torch.float32):
-            raise ValueError(f"tape must be float32 [>={spec.max_steps}][{lanes}][4]")
+            raise ValueError(f"tape must be float32 [>={spec.max_steps}][{lanes}][3]")
     if tally and (out.tally is None or tuple(out.tally.shape) != (spec.n_variants, 3)):
         raise ValueError(f"tally must be float64 [{spec.n_variants}][3]")
 

@@ -84,7 +84,7 @@ struct DevRun {
     int64_t lanes;               // n_variants * n
     const float *scales;         // [n_variants][n_mag] or nullptr
     double *ckpt;                // [n_ckpt][6][lanes] or nullptr
-    float *tape;                 // [max_steps][lanes][4] or nullptr
+    float *tape;                 // [max_steps][lanes][3] or nullptr
     int32_t *trace;
     int64_t n_trace;
     int32_t trace_steps;

@@ -798,9 +798,11 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
         uz = -f;
         kick(L, p2, ux, uy, uz);
     }
-    if (TAPE) {
-        reinterpret_cast<float4 *>(R.tape)[(size_t)L.k * R.lanes + L.g] =
-            make_float4(ux, uy, uz, __int_as_float(vol));
+    if (TAPE) {   // the local kick; the replay finds the volume again from the state
+        float *t = R.tape + ((size_t)L.k * R.lanes + L.g) * 3;
+        t[0] = ux;
+        t[1] = uy;
+        t[2] = uz;
     }
     if (TRACE && L.g < R.n_trace && L.k < R.trace_steps) {
         int32_t *tr = R.trace + ((size_t)L.g * R.trace_steps + L.k) * 3;
@@ -1224,28 +1226,29 @@ struct Float3r {
 // or, rarely, one unit in the last place (the FP64 state and its FP32
 // rounding differ by ~1e-8 relative), which is what the FP32 Jacobians
 // built from it need.
-__device__ __forceinline__ float3 kick_again(float3 p0, float4 rec) {
+__device__ __forceinline__ float3 kick_again(float3 p0, float3 u) {
     Lane K;
     K.px = (double)p0.x;
     K.py = (double)p0.y;
     K.pz = (double)p0.z;
     const double p2 = K.px * K.px + K.py * K.py + K.pz * K.pz;
-    kick(K, p2, rec.x, rec.y, rec.z);
+    kick(K, p2, u.x, u.y, u.z);
     return stage0(K);
 }
 
-// Re-run one step of a segment with its recorded kick and volume (the
-// arithmetic of advance(), so the same bits).  B caches the field of volume
-// bvol.  Returns the FP32 momentum the RK4 stages started from.
+// Re-run one step of a segment with its recorded kick (the arithmetic of
+// advance(), so the same bits).  The volume is looked up again from the
+// state, which is the forward's to the bit, so it is the forward's volume.
+// B caches the field of volume bvol.  Returns the volume.
 template <bool MAP>
-__device__ __forceinline__ float3 replay_step(Lane &L, const Tables &T, const Lds &S,
-                                              const DevRun &R, const StepConst &sc, int var,
-                                              float4 rec) {
-    const int vol = __float_as_int(rec.w);
+__device__ __forceinline__ int replay_step(Lane &L, const Tables &T, const Lds &S,
+                                           const DevRun &R, const StepConst &sc, int var,
+                                           float3 u) {
+    const int vol = locate(L, T, S);
     const int mat = vol >= 0 ? S.mat[vol] : -1;
     if (mat >= 0) {
         const double p2 = L.px * L.px + L.py * L.py + L.pz * L.pz;
-        kick(L, p2, rec.x, rec.y, rec.z);
+        kick(L, p2, u.x, u.y, u.z);
     }
     if (vol != L.bvol) {
         const float3 b = box_field(T, S, R, vol, var);
@@ -1257,7 +1260,7 @@ __device__ __forceinline__ float3 replay_step(Lane &L, const Tables &T, const Ld
     const float3 B = add_map<MAP>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
     const float3 a0 = stage0(L);
     rk4_from(L, a0, B, sc);
-    return a0;
+    return vol;
 }
 
 // The segment's start momenta are kept either in LDS (LDSH) or in a per-lane
@@ -1277,6 +1280,12 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
     double *sgs = reinterpret_cast<double *>(smem + ((T.lds.bytes + 15) & ~15)) + threadIdx.x;
     float *hist = reinterpret_cast<float *>(smem + ((T.lds.bytes + 15) & ~15) +
                                             (size_t)n_mag * bd * sizeof(double)) + threadIdx.x;
+    // volume of every step of the segment, found again by the replay and
+    // read back by the reverse sweep: [step][thread], one byte each
+    int8_t *vh = reinterpret_cast<int8_t *>(smem + ((T.lds.bytes + 15) & ~15) +
+                                           (size_t)n_mag * bd * sizeof(double) +
+                                           (LDSH ? (size_t)kCkptEvery * 3 * bd * sizeof(float) : 0)) +
+                 threadIdx.x;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = g0 < R.lanes;
     const int64_t g = live ? g0 : R.lanes - 1;   // lanes past the end idle below
@@ -1320,9 +1329,13 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
             L.py = c[4 * lanes];
             L.pz = c[5 * lanes];
             L.q = q;
-            // kick records of the segment: one float4 per (step, lane)
-            const float4 *rec = reinterpret_cast<const float4 *>(R.tape) + (size_t)k0 * lanes + g;
+            // kick records of the segment: three floats per (step, lane)
+            const float *rec = R.tape + ((size_t)k0 * lanes + g) * 3;
             L.bvol = -2;
+            L.vol = -1;                  // lookup caches start empty
+            L.slab = -1;
+            L.zlo = INFINITY;
+            L.zhi = -INFINITY;
             // history of the segment: the pre-kick momentum p0 of every step
             // (FP32), [step][3][thread] in LDS (LDSH) or one 12-byte record per
             // (step, lane) in device memory.  The stage-0 momentum a0 is formed
@@ -1342,14 +1355,15 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
                 scratch + (size_t)kCkptEvery * sizeof(Float3r) * lanes) + g;
             // running pointers (one 64-bit add per array and step) rather
             // than (k - k0) * lanes products
-            const float4 *rp = rec;
+            const size_t rs = (size_t)lanes * 3;     // record stride between steps
+            const float *rp = rec;
             Float3r *h3p = h3;
             double *hrp = hr;
-            float4 next = *rp;
+            float3 next = make_float3(rp[0], rp[1], rp[2]);
             for (int k = k0; k < k1; ++k) {
-                const float4 cur = next;
-                rp += lanes;
-                if (k + 1 < k1) next = *rp;
+                const float3 cur = next;
+                rp += rs;
+                if (k + 1 < k1) next = make_float3(rp[0], rp[1], rp[2]);
                 const float p0x = (float)L.px, p0y = (float)L.py, p0z = (float)L.pz;
                 if (MAP) {
                     hrp[0] = L.x;
@@ -1357,7 +1371,7 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
                     hrp[2 * lanes] = L.z;
                     hrp += 3 * lanes;
                 }
-                replay_step<MAP>(L, T, S, R, sc, var, cur);
+                vh[(k - k0) * bd] = (int8_t)replay_step<MAP>(L, T, S, R, sc, var, cur);
                 if (LDSH) {
                     float *h = hp + (size_t)(k - k0) * 3 * hs;
                     h[0] = p0x;
@@ -1374,10 +1388,10 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
             double acc = 0.0;
             // the reverse sweep loads step k-1's kick record and history
             // while it works on step k
-            rp -= lanes;                 // step k1 - 1
+            rp -= rs;                    // step k1 - 1
             h3p -= lanes;
             hrp -= 3 * lanes;
-            next = *rp;
+            next = make_float3(rp[0], rp[1], rp[2]);
             Float3r nP{0.f, 0.f, 0.f};
             double nx = 0.0, ny = 0.0, nz = 0.0;
             if (!LDSH) nP = *h3p;
@@ -1387,12 +1401,12 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
                 nz = hrp[2 * lanes];
             }
             for (int k = k1 - 1; k >= k0; --k) {
-                const float4 cur = next;
+                const float3 cur = next;
                 const Float3r P = nP;
                 const double rx = nx, ry = ny, rz = nz;
                 if (k > k0) {
-                    rp -= lanes;
-                    next = *rp;
+                    rp -= rs;
+                    next = make_float3(rp[0], rp[1], rp[2]);
                     if (!LDSH) {
                         h3p -= lanes;
                         nP = *h3p;
@@ -1411,7 +1425,7 @@ k_adjoint(Tables T, DevRun R, DevIO io, const double *g_out,
                 } else {
                     p0 = make_float3(P.x, P.y, P.z);
                 }
-                const int vol = __float_as_int(cur.w);
+                const int vol = vh[(k - k0) * bd];
                 const float3 a0 = (vol >= 0 && S.mat[vol] >= 0) ? kick_again(p0, cur) : p0;
                 if (vol != bvol) {
                     bb = box_field(T, S, R, vol, var);
@@ -1662,6 +1676,7 @@ hipError_t launch_adjoint(const Tables &T, const DevRun &R, const DevIO &io,
     const bool ldsh = lds_history && !map;
     size_t shm = (size_t)((T.lds.bytes + 15) & ~15) + (size_t)T.geom.n_mag * block * sizeof(double);
     if (ldsh) shm += (size_t)kCkptEvery * 3 * block * sizeof(float);   // p0 per step
+    shm += (size_t)kCkptEvery * block;                                   // volume per step
     char *sc = reinterpret_cast<char *>(scratch);
     if (map)
         hipLaunchKernelGGL((k_adjoint<true, false>), dim3((unsigned)grid), dim3(block), shm, s, T, R, io, g_out, g_in, gs_lane, sc);

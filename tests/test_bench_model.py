@@ -66,9 +66,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_adjoint_bytes():
-    """Replay-and-reverse adjoint: 59 bytes per muon-step (kick record read
-    twice, 12-byte history written and read, a 48-byte checkpoint per 16
-    steps) and 112 + 8 n_mag bytes per lane."""
-    assert bench.adjoint_bytes(1600, 0, 8) == 1600 * 59
+    """Replay-and-reverse adjoint: 51 bytes per muon-step (12-byte kick
+    record read twice, 12-byte history written and read, a 48-byte
+    checkpoint per 16 steps) and 112 + 8 n_mag bytes per lane."""
+    assert bench.adjoint_bytes(1600, 0, 8) == 1600 * 51
     assert bench.adjoint_bytes(0, 10, 8) == 10 * (112 + 64)
-    assert bench.adjoint_bytes(16, 1, 0) == 16 * 59 + 112
+    assert bench.adjoint_bytes(16, 1, 0) == 16 * 51 + 112
