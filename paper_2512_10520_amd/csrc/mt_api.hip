@@ -1071,6 +1071,7 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
     for (int a = 0; a < 3; ++a) {
         F.lo[a] = lo[a];
         F.inv_d[a] = (double)(n[a] - 1) / (hi[a] - lo[a]);
+        F.umax[a] = (double)(n[a] - 1);
     }
     tables_changed();
     return MT_OK;

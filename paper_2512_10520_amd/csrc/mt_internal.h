@@ -62,6 +62,7 @@ struct DevField {
     int32_t nx, ny, nz;
     double lo[3];
     double inv_d[3];             // (n - 1) / (hi - lo)
+    double umax[3];              // n - 1: the largest grid coordinate inside the map
 };
 
 // Byte offsets of the tables staged in LDS by every block.

@@ -442,13 +442,19 @@ struct Corner8 {
     float fx, fy, fz;
 };
 
+// Inside the map's node range on all three axes (closed): six compares
+// combined without branches, against the node counts as doubles.
+__device__ __forceinline__ bool in_map(const DevField &F, double u, double v, double w) {
+    return (u >= 0.0) & (u <= F.umax[0]) & (v >= 0.0) & (v <= F.umax[1]) & (w >= 0.0) &
+           (w <= F.umax[2]);
+}
+
 __device__ __forceinline__ bool map_cell(const DevField &F, double x, double y, double z,
                                          Corner8 &c) {
     const double u = (x - F.lo[0]) * F.inv_d[0];
     const double v = (y - F.lo[1]) * F.inv_d[1];
     const double w = (z - F.lo[2]) * F.inv_d[2];
-    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
-          w >= 0.0 && w <= (double)(F.nz - 1)))
+    if (!in_map(F, u, v, w))
         return false;
     const int i = min((int)u, F.nx - 2), j = min((int)v, F.ny - 2), k = min((int)w, F.nz - 2);
     c.fx = (float)(u - (double)i);
@@ -513,8 +519,7 @@ __device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, flo
     const double u = (L.x - F.lo[0]) * F.inv_d[0];
     const double v = (L.y - F.lo[1]) * F.inv_d[1];
     const double w = (L.z - F.lo[2]) * F.inv_d[2];
-    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
-          w >= 0.0 && w <= (double)(F.nz - 1)))
+    if (!in_map(F, u, v, w))
         return B;
     const int i = min((int)u, F.nx - 2), j = min((int)v, F.ny - 2), k = min((int)w, F.nz - 2);
     const int cell = (k * (F.ny - 1) + j) * (F.nx - 1) + i;
@@ -551,8 +556,7 @@ __device__ __forceinline__ float3 add_nearest_cached(Lane &L, const DevField &F,
     const double u = (L.x - F.lo[0]) * F.inv_d[0];
     const double v = (L.y - F.lo[1]) * F.inv_d[1];
     const double w = (L.z - F.lo[2]) * F.inv_d[2];
-    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
-          w >= 0.0 && w <= (double)(F.nz - 1)))
+    if (!in_map(F, u, v, w))
         return B;
     const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
               k = min((int)(w + 0.5), F.nz - 1);
@@ -574,8 +578,7 @@ __device__ __forceinline__ float3 map_nearest(const DevField &F, double x, doubl
     const double u = (x - F.lo[0]) * F.inv_d[0];
     const double v = (y - F.lo[1]) * F.inv_d[1];
     const double w = (z - F.lo[2]) * F.inv_d[2];
-    if (!(u >= 0.0 && u <= (double)(F.nx - 1) && v >= 0.0 && v <= (double)(F.ny - 1) &&
-          w >= 0.0 && w <= (double)(F.nz - 1)))
+    if (!in_map(F, u, v, w))
         return make_float3(0.f, 0.f, 0.f);
     const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
               k = min((int)(w + 0.5), F.nz - 1);
