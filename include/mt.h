@@ -193,7 +193,7 @@ int mt_load_blocks(int32_t n, const double *block, const int32_t *material, cons
  * cell-major copy, the 8 corner values of each cell in one 128-byte record
  * (128 (nx-1)(ny-1)(nz-1) bytes), so that a trilinear lookup reads one cache
  * line, and a node-major copy (16 nx ny nz bytes) for the nearest node.
- * Limit: nx ny nz < 2^31 (MT_ERR_LIMIT).
+ * Limits: nx ny nz < 2^31, nx < 2^24 and ny nz < 2^24 (MT_ERR_LIMIT).
  * Errors: MT_ERR_INVALID_ARG, MT_ERR_OOM, MT_ERR_HIP.
  */
 int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const double *hi,

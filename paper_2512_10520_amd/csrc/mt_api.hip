@@ -1029,6 +1029,9 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
     if ((size_t)nx * ny * nz > 0x7FFFFFFFull)
         return fail(MT_ERR_LIMIT, "the field map has %zu nodes, more than 2^31 - 1",
                     (size_t)nx * ny * nz);
+    if ((size_t)nx >= (1u << 24) || (size_t)ny * nz >= (1u << 24))
+        return fail(MT_ERR_LIMIT, "the field map needs nx < 2^24 and ny nz < 2^24 (cell and "
+                                  "node indices are formed with 24-bit products)");
     for (size_t i = 0; i < 3 * (size_t)nx * ny * nz; ++i)
         if (!std::isfinite(b[i]))
             return fail(MT_ERR_INVALID_ARG, "field map value %zu (node %zu, component %zu) is "
@@ -1072,6 +1075,7 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
         F.lo[a] = lo[a];
         F.inv_d[a] = (double)(n[a] - 1) / (hi[a] - lo[a]);
         F.umax[a] = (double)(n[a] - 1);
+        F.off[a] = -lo[a] * F.inv_d[a];
     }
     tables_changed();
     return MT_OK;

@@ -63,6 +63,7 @@ struct DevField {
     double lo[3];
     double inv_d[3];             // (n - 1) / (hi - lo)
     double umax[3];              // n - 1: the largest grid coordinate inside the map
+    double off[3];               // -lo (n - 1) / (hi - lo): u = x inv_d + off
 };
 
 // Byte offsets of the tables staged in LDS by every block.

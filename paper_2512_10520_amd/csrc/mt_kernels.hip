@@ -442,6 +442,17 @@ struct Corner8 {
     float fx, fy, fz;
 };
 
+// Grid coordinates of a point: u = (x - lo) / d as one FMA, x (n - 1)/(hi -
+// lo) - lo (n - 1)/(hi - lo), with both factors formed on the host.  Every
+// map lookup (forward, replay, stage points) uses this, so the forward and
+// the adjoint's replay see the same cells and weights.
+__device__ __forceinline__ void map_coords(const DevField &F, double x, double y, double z,
+                                           double &u, double &v, double &w) {
+    u = fma(x, F.inv_d[0], F.off[0]);
+    v = fma(y, F.inv_d[1], F.off[1]);
+    w = fma(z, F.inv_d[2], F.off[2]);
+}
+
 // Inside the map's node range on all three axes (closed): six compares
 // combined without branches, against the node counts as doubles.
 __device__ __forceinline__ bool in_map(const DevField &F, double u, double v, double w) {
@@ -451,9 +462,8 @@ __device__ __forceinline__ bool in_map(const DevField &F, double u, double v, do
 
 __device__ __forceinline__ bool map_cell(const DevField &F, double x, double y, double z,
                                          Corner8 &c) {
-    const double u = (x - F.lo[0]) * F.inv_d[0];
-    const double v = (y - F.lo[1]) * F.inv_d[1];
-    const double w = (z - F.lo[2]) * F.inv_d[2];
+    double u, v, w;
+    map_coords(F, x, y, z, u, v, w);
     if (!in_map(F, u, v, w))
         return false;
     const int i = min((int)u, F.nx - 2), j = min((int)v, F.ny - 2), k = min((int)w, F.nz - 2);
@@ -516,13 +526,14 @@ __device__ __forceinline__ float3 add_map(const Tables &T, float3 B, double x, d
 // record is loaded only when the lane enters a new cell.  Same values and
 // arithmetic as map_cell + trilerp.
 __device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, float3 B) {
-    const double u = (L.x - F.lo[0]) * F.inv_d[0];
-    const double v = (L.y - F.lo[1]) * F.inv_d[1];
-    const double w = (L.z - F.lo[2]) * F.inv_d[2];
+    double u, v, w;
+    map_coords(F, L.x, L.y, L.z, u, v, w);
     if (!in_map(F, u, v, w))
         return B;
     const int i = min((int)u, F.nx - 2), j = min((int)v, F.ny - 2), k = min((int)w, F.nz - 2);
-    const int cell = (k * (F.ny - 1) + j) * (F.nx - 1) + i;
+    // 24-bit products: the loader keeps nx and ny nz below 2^24
+    const int cell = (int)__umul24(__umul24((uint32_t)k, (uint32_t)(F.ny - 1)) + (uint32_t)j,
+                                   (uint32_t)(F.nx - 1)) + i;
     if (cell != L.mcell) {
         const float4 *b = F.map + (size_t)cell * 8;
 #pragma unroll
@@ -553,14 +564,14 @@ __device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, flo
 // Nearest node with the last node's value kept in registers (mcell holds the
 // node index, mc[0..2] its value).
 __device__ __forceinline__ float3 add_nearest_cached(Lane &L, const DevField &F, float3 B) {
-    const double u = (L.x - F.lo[0]) * F.inv_d[0];
-    const double v = (L.y - F.lo[1]) * F.inv_d[1];
-    const double w = (L.z - F.lo[2]) * F.inv_d[2];
+    double u, v, w;
+    map_coords(F, L.x, L.y, L.z, u, v, w);
     if (!in_map(F, u, v, w))
         return B;
     const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
               k = min((int)(w + 0.5), F.nz - 1);
-    const int node = (k * F.ny + j) * F.nx + i;
+    const int node = (int)__umul24(__umul24((uint32_t)k, (uint32_t)F.ny) + (uint32_t)j,
+                                   (uint32_t)F.nx) + i;
     if (node != L.mcell) {
         const float4 q = F.nodes[node];
         L.mc[0] = q.x;
@@ -575,9 +586,8 @@ __device__ __forceinline__ float3 add_nearest_cached(Lane &L, const DevField &F,
 // (half-way points take the higher node), zero outside the grid.  One
 // 16-byte load from the node-major copy of the map.
 __device__ __forceinline__ float3 map_nearest(const DevField &F, double x, double y, double z) {
-    const double u = (x - F.lo[0]) * F.inv_d[0];
-    const double v = (y - F.lo[1]) * F.inv_d[1];
-    const double w = (z - F.lo[2]) * F.inv_d[2];
+    double u, v, w;
+    map_coords(F, x, y, z, u, v, w);
     if (!in_map(F, u, v, w))
         return make_float3(0.f, 0.f, 0.f);
     const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
