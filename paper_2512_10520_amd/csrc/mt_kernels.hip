@@ -521,13 +521,16 @@ __device__ __forceinline__ float3 add_map(const Tables &T, float3 B, double x, d
     return B;
 }
 
-// Trilinear map at the lane's position with the current cell's corners kept
-// in registers: consecutive 2 cm steps mostly stay in one cell, so the 128-byte
-// record is loaded only when the lane enters a new cell.  Same values and
-// arithmetic as map_cell + trilerp.
-__device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, float3 B) {
+// Trilinear map at a point (the lane's position, or an RK4 stage point near
+// it) with the lane's current cell's corners kept in registers: consecutive
+// 2 cm steps and their stage points mostly stay in one cell, so the 128-byte
+// record is loaded only when the point lies in another cell (which then
+// becomes the lane's cell).  Same values and arithmetic as map_cell +
+// trilerp.
+__device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, float3 B, double x,
+                                                  double y, double z) {
     double u, v, w;
-    map_coords(F, L.x, L.y, L.z, u, v, w);
+    map_coords(F, x, y, z, u, v, w);
     if (!in_map(F, u, v, w))
         return B;
     const int i = min((int)u, F.nx - 2), j = min((int)v, F.ny - 2), k = min((int)w, F.nz - 2);
@@ -563,9 +566,10 @@ __device__ __forceinline__ float3 add_map_cached(Lane &L, const DevField &F, flo
 
 // Nearest node with the last node's value kept in registers (mcell holds the
 // node index, mc[0..2] its value).
-__device__ __forceinline__ float3 add_nearest_cached(Lane &L, const DevField &F, float3 B) {
+__device__ __forceinline__ float3 add_nearest_cached(Lane &L, const DevField &F, float3 B,
+                                                      double x, double y, double z) {
     double u, v, w;
-    map_coords(F, L.x, L.y, L.z, u, v, w);
+    map_coords(F, x, y, z, u, v, w);
     if (!in_map(F, u, v, w))
         return B;
     const int i = min((int)(u + 0.5), F.nx - 1), j = min((int)(v + 0.5), F.ny - 1),
@@ -705,16 +709,19 @@ __device__ __forceinline__ float3 map_field(const Tables &T, float3 B, double x,
     }
 }
 
-// Field at a stage point: scaled field of the box holding it plus the map.
+// Field at a stage point: scaled field of the box holding it plus the map,
+// read through the lane's cached map cell or node.
 template <unsigned F>
 __device__ __forceinline__ float3 field_at_point(const Tables &T, const Lds &S, const DevRun &R,
-                                                 const Lane &L, double x, double y, double z) {
+                                                 Lane &L, double x, double y, double z) {
     const int s = find_slab(S, T.geom.n_slab, z, L.slab);
     const int vol = find_box(S, s, x, y);
     float3 B;
     if (vol == L.bvol) B = make_float3(L.bx, L.by, L.bz);
     else B = box_field(T, S, R, vol, L.var);
-    return map_field<F>(T, B, x, y, z);
+    if constexpr ((F & kMap) != 0 && (F & kNearest) == 0) return add_map_cached(L, T.field, B, x, y, z);
+    else if constexpr ((F & kNearest) != 0) return add_nearest_cached(L, T.field, B, x, y, z);
+    else return B;
 }
 
 // RK4 with the field evaluated afresh at each stage position (stage s sits
@@ -832,9 +839,9 @@ __device__ __forceinline__ bool advance(Lane &L, const Tables &T, const Lds &S, 
     }
     float3 B;
     if constexpr ((F & kMap) != 0 && (F & kNearest) == 0)
-        B = add_map_cached(L, T.field, make_float3(L.bx, L.by, L.bz));
+        B = add_map_cached(L, T.field, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
     else if constexpr ((F & kNearest) != 0)
-        B = add_nearest_cached(L, T.field, make_float3(L.bx, L.by, L.bz));
+        B = add_nearest_cached(L, T.field, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
     else
         B = map_field<F>(T, make_float3(L.bx, L.by, L.bz), L.x, L.y, L.z);
     if constexpr ((F & kStages) != 0) rk4_stages<F>(L, B, T, S, R, sc);
