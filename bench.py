@@ -51,7 +51,8 @@ VALU_BASE_LANE_OPS = SIMDS * 16 * CLOCK_HZ
 # (FP32, sin and cos), kick + rotation 30 (FP32, one rsq, the FP64 update of
 # p and its conversions), field 1, RK4 103 (FP32 stages with 4 rsq, FP64
 # accumulation and conversions), loop 2.  A vacuum step in zero field is 40.
-# The field map adds 30 (8 corner loads, 21 lerps, FP64 cell coordinates);
+# The field map adds 30 (FP64 cell coordinates and index, and 15 FP32 for the
+# interpolation: a lower bound, the cell polynomial takes 21 FMAs);
 # zero-field material steps replace the RK4 by the straight-line update
 # (-84).  A convex-block lookup replaces the box lookup by one candidate's
 # sign test (grid cell, slice and edge products in FP64: +43).  In the

@@ -190,11 +190,14 @@ int mt_load_blocks(int32_t n, const double *block, const int32_t *material, cons
  *   b   host float [nz][ny][nx][3] tesla, every value finite; NULL unloads
  *       the map.
  * Requires nx, ny, nz >= 2 and lo < hi on every axis.  The device holds a
- * cell-major copy, the 8 corner values of each cell in one 128-byte record
- * (128 (nx-1)(ny-1)(nz-1) bytes), so that a trilinear lookup reads one cache
- * line, and a node-major copy (16 nx ny nz bytes) for the nearest node.
+ * cell-major copy, each cell's trilinear interpolant as 8 polynomial
+ * coefficients (formed in double precision from the cell's 8 corner values
+ * and rounded to float) in one 128-byte record (128 (nx-1)(ny-1)(nz-1)
+ * bytes), so that a trilinear lookup reads one cache line, and a node-major
+ * copy (16 nx ny nz bytes) for the nearest node.
  * Limits: nx ny nz < 2^31, nx < 2^24 and ny nz < 2^24 (MT_ERR_LIMIT).
- * Errors: MT_ERR_INVALID_ARG, MT_ERR_OOM, MT_ERR_HIP.
+ * Errors: MT_ERR_INVALID_ARG (also when a coefficient overflows float, which
+ * needs values near FLT_MAX), MT_ERR_OOM, MT_ERR_HIP.
  */
 int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const double *hi,
                   const float *b);

@@ -147,8 +147,8 @@ class DeviceMuons:
 
     @staticmethod
     def from_host(m, device="cuda") -> "DeviceMuons":
-        st = torch.from_numpy(np.ascontiguousarray(m.stacked(), dtype=np.float64)).to(device)
-        q = torch.from_numpy(np.ascontiguousarray(m.q, dtype=np.int8)).to(device)
+        st = torch.from_numpy(np.array(m.stacked(), dtype=np.float64, order="C")).to(device)
+        q = torch.from_numpy(np.array(m.q, dtype=np.int8, order="C")).to(device)
         return DeviceMuons(st.contiguous(), q.contiguous())
 
     def c_struct(self) -> MtMuons:

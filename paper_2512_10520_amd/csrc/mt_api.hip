@@ -1021,9 +1021,12 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] > lo[a]))
             return fail(MT_ERR_INVALID_ARG, "field bounds must be finite with hi > lo (axis %d)", a);
-    // Cell-major copy: the 8 corner values of every cell in one 128-byte
-    // record (x fastest: c000 c100 c010 c110 c001 c101 c011 c111), so a
-    // lookup touches one cache line instead of four.
+    // Cell-major copy: every cell's trilinear interpolant in one 128-byte
+    // record, as the coefficients k0..k7 of
+    //   k0 + k1 fx + k2 fy + k3 fz + k4 fx fy + k5 fx fz + k6 fy fz + k7 fx fy fz
+    // in the fractional coordinates of the cell (formed in FP64 from the 8
+    // corner values, then rounded), so a lookup touches one cache line
+    // instead of four and evaluates 7 FMAs per component.
     const size_t cx = (size_t)nx - 1, cy = (size_t)ny - 1, cz = (size_t)nz - 1;
     const size_t cells = cx * cy * cz;
     if ((size_t)nx * ny * nz > 0x7FFFFFFFull)
@@ -1046,11 +1049,33 @@ int mt_load_field(int32_t nx, int32_t ny, int32_t nz, const double *lo, const do
         for (size_t j = 0; j < cy; ++j)
             for (size_t i = 0; i < cx; ++i) {
                 float4 *rec = m.data() + ((k * cy + j) * cx + i) * 8;
-                for (int c = 0; c < 8; ++c) {
-                    const size_t node = ((k + (c >> 2)) * (size_t)ny + (j + ((c >> 1) & 1))) * nx +
-                                        (i + (c & 1));
-                    rec[c] = make_float4(b[3 * node], b[3 * node + 1], b[3 * node + 2], 0.f);
+                float kc[8][3];
+                for (int a = 0; a < 3; ++a) {
+                    // corner values C[c], c = dx + 2 dy + 4 dz
+                    double C[8];
+                    for (int c = 0; c < 8; ++c) {
+                        const size_t node = ((k + (c >> 2)) * (size_t)ny + (j + ((c >> 1) & 1))) *
+                                                nx + (i + (c & 1));
+                        C[c] = (double)b[3 * node + a];
+                    }
+                    const double q[8] = {
+                        C[0],
+                        C[1] - C[0],
+                        C[2] - C[0],
+                        C[4] - C[0],
+                        C[3] - C[1] - C[2] + C[0],
+                        C[5] - C[1] - C[4] + C[0],
+                        C[6] - C[2] - C[4] + C[0],
+                        C[7] - C[3] - C[5] - C[6] + C[1] + C[2] + C[4] - C[0]};
+                    for (int c = 0; c < 8; ++c) {
+                        kc[c][a] = (float)q[c];
+                        if (!std::isfinite(kc[c][a]))
+                            return fail(MT_ERR_INVALID_ARG,
+                                        "field map cell (%zu, %zu, %zu): an interpolation "
+                                        "coefficient overflows single precision", i, j, k);
+                    }
                 }
+                for (int c = 0; c < 8; ++c) rec[c] = make_float4(kc[c][0], kc[c][1], kc[c][2], 0.f);
             }
     // Node-major copy for the nearest-node lookup (one value per lookup).
     std::vector<float4> nd;

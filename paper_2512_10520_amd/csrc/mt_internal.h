@@ -56,8 +56,9 @@ struct DevGeom {
 };
 
 struct DevField {
-    const float4 *map;           // cell-major [nz-1][ny-1][nx-1][8 corners] (bx, by, bz, 0),
-                                 // corner c = (c & 1, c >> 1 & 1, c >> 2) offsets; nullptr = no map
+    const float4 *map;           // cell-major [nz-1][ny-1][nx-1][8] (bx, by, bz, 0): the cell's
+                                 // trilinear interpolant as coefficients of 1, fx, fy, fz, fx fy,
+                                 // fx fz, fy fz, fx fy fz; nullptr = no map
     const float4 *nodes;         // node-major [nz][ny][nx] (bx, by, bz, 0), for the nearest node
     int32_t nx, ny, nz;
     double lo[3];
