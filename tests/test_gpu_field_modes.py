@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2512_10520_amd import workloads as W
+from tests import _custom as CU
 from tests._parity import compare, gpu_run, map_deltas, oracle_run
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +66,41 @@ def test_stage_field_box_geometries(name, n):
         s = compare(g, o, sel=sel, trace_rows=1000 if v == 0 else 0,
                     label=f"{name} stages v={v}")
         print(name, "stages", v, s)
+
+
+@pytest.mark.parametrize("interp", [0, 1], ids=["trilinear", "nearest"])
+@pytest.mark.parametrize("stage", [0, 1], ids=["held", "stages"])
+def test_uniform_map_equals_uniform_box_field(interp, stage):
+    """A map whose every node holds the same field B gives B itself at every
+    point inside it: the cell polynomial's non-constant coefficients are
+    exactly zero and its constant one is B, and the nearest node is B.  So
+    transport with that map and no box field equals, bit for bit, transport
+    with the uniform box field B and no map (every muon stays inside the
+    map: the world bounds lie within it)."""
+    B = (0.3, 1.5, -0.2)
+    box = [(-5.0, 5.0, -5.0, 5.0, 0.0, 20.0)]
+    world = (4.0, 4.0, 15.0)
+    rng = np.random.default_rng(5)
+    n = 4000
+    mu = CU.muons(rng.uniform(-0.5, 0.5, n), rng.uniform(-0.5, 0.5, n), 0.0,
+                  rng.normal(0.0, 0.5, n), rng.normal(0.0, 0.5, n), rng.uniform(5.0, 50.0, n),
+                  rng.choice([-1, 1], n))
+    nx, ny, nz = 11, 7, 23
+    nodes = np.empty((nz, ny, nx, 3), np.float32)
+    nodes[...] = np.asarray(B, np.float32)
+    fmap = W.FieldMap(lo=np.array([-5.0, -5.0, -1.0]), hi=np.array([5.0, 5.0, 21.0]), b=nodes)
+    hist = CU.flat_histograms()
+    with_box = CU.workload(hist, CU.geometry(box, [0], b_box=[B], world=world), mu,
+                           interp=interp, stage_field=stage)
+    with_map = CU.workload(hist, CU.geometry(box, [0], world=world), mu, field=fmap,
+                           interp=interp, stage_field=stage)
+    a = gpu_run(with_box)
+    b = gpu_run(with_map)
+    for k in ("state", "status", "n_steps", "volume"):
+        assert np.array_equal(a[k], b[k]), k
+    # the field bends the tracks: they differ from a run without any field
+    c = gpu_run(CU.workload(hist, CU.geometry(box, [0], world=world), mu))
+    assert not np.array_equal(a["state"], c["state"])
 
 
 def test_field_modes_rejected_with_checkpoints():
